@@ -1,0 +1,236 @@
+"""Pins of the oracle's collective steps (histogram, wake convolution and
+kick, moments, loss reordering) and of its tracking driver, against brute
+force in exact arithmetic, closed forms and invariants."""
+import math
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.signal import fftconvolve
+
+from paper_1710_07350_amd import inputs
+from paper_1710_07350_amd.inputs import Element
+
+mp.mp.dps = 40
+
+
+# ------------------------------------------------------------------ histogram
+def test_histogram_exact_rational_bins(orc):
+    rng = np.random.default_rng(1)
+    s = rng.normal(0, 1e-3, 20000)
+    lost = np.full(20000, -1, np.int64)
+    lost[::7] = 5                            # lost particles are not binned
+    nb = 256
+    rg, cnt = orc.histogram(s, lost, nb)
+    alive = s[lost < 0]
+    assert rg[0] == alive.min() and rg[1] == alive.max()
+    assert cnt.sum() == alive.size
+    smin, smax = Fraction(rg[0]), Fraction(rg[1])
+    ref = np.zeros(nb, np.int64)
+    for v in alive:
+        b = math.floor((Fraction(v) - smin) * nb / (smax - smin))
+        ref[min(b, nb - 1)] += 1
+    assert np.array_equal(cnt, ref)
+
+
+def test_histogram_degenerate(orc):
+    s = np.full(10, 0.25)
+    rg, cnt = orc.histogram(s, np.full(10, -1, np.int64), 8)
+    assert tuple(rg) == (0.25, 0.25) and cnt[0] == 10 and cnt[1:].sum() == 0
+    rg, cnt = orc.histogram(s, np.full(10, 3, np.int64), 8)     # nobody alive
+    assert tuple(rg) == (0.0, 0.0) and cnt.sum() == 0
+
+
+# ------------------------------------------------------------------ convolution
+@pytest.mark.parametrize("nb", [4, 9, 16])
+def test_convolution_exact_rational(orc, nb):
+    rng = np.random.default_rng(nb)
+    c = rng.integers(0, 1000, nb).astype(np.uint32)
+    w = rng.normal(0, 1, nb)
+    v = orc.convolve(c, w)
+    for i in range(nb):
+        exact = sum(Fraction(int(c[j])) * Fraction(w[i - j]) for j in range(i + 1))
+        bound = (i + 1) * 2.0 ** -53 * sum(abs(int(c[j]) * w[i - j]) for j in range(i + 1))
+        assert abs(float(Fraction(v[i]) - exact)) <= bound
+
+
+def test_convolution_delta_and_fft(orc):
+    nb = 1024
+    w = orc.wake_table(0.0, 8e-3, nb, 10e-12, 2 * math.pi * 50e9)
+    c = np.zeros(nb, np.uint32)
+    c[37] = 1
+    v = orc.convolve(c, w)
+    assert np.array_equal(v[37:], w[:nb - 37]) and not v[:37].any()
+    rng = np.random.default_rng(2)
+    c = rng.integers(0, 5000, nb).astype(np.uint32)
+    v = orc.convolve(c, w)
+    ref = fftconvolve(c.astype(float), w)[:nb]
+    scale = np.convolve(np.abs(c.astype(float)), np.abs(w))[:nb]
+    assert np.all(np.abs(v - ref) <= 1e-12 * scale.max())
+
+
+def test_wake_table_closed_form(orc):
+    nb, smin, smax, tau0, om = 1024, -3e-3, 5e-3, 10e-12, 2 * math.pi * 50e9
+    w = orc.wake_table(smin, smax, nb, tau0, om)
+    assert w[0] == 0.5
+    dt = ((smax - smin) / nb) / 299792458.0
+    for m in range(1, nb, 13):
+        t = mp.mpf(m) * mp.mpf(dt)
+        exact = mp.exp(-t / tau0) * mp.cos(om * t)
+        assert abs(float(exact) - w[m]) < 2e-15
+
+
+def test_wake_constant_wake_beam_loading(orc):
+    """A constant wake (tau0 -> inf, omega = 0) makes V[i] = (particles ahead)
+    + half of the own bin, so the total kick is (sum c)^2 / 2 and only
+    trailing particles feel leading ones (causality)."""
+    nb = 64
+    rng = np.random.default_rng(3)
+    s = rng.normal(0, 1e-3, 4000)
+    rg, cnt = orc.histogram(s, np.full(4000, -1, np.int64), nb)
+    w = orc.wake_table(rg[0], rg[1], nb, 1e300, 0.0)
+    assert np.all(w[1:] == 1.0)
+    v = orc.convolve(cnt, w)
+    ahead = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    assert np.array_equal(v, ahead + 0.5 * cnt)
+    assert math.isclose(float((cnt * v).sum()), 0.5 * float(cnt.sum()) ** 2, rel_tol=1e-15)
+
+
+def test_wake_kick_interpolation_by_hand(orc):
+    v = np.array([1.0, 2.0, 4.0, 8.0])
+    rg = np.array([0.0, 4.0])                # bins of width 1, centres at 0.5,1.5,2.5,3.5
+    s = np.array([0.0, 0.5, 1.0, 2.5, 3.0, 3.5, 4.0])
+    z = np.zeros((6, len(s)))
+    z[4] = s
+    b = orc.Beam(z, np.arange(len(s), dtype=np.uint32), np.full(len(s), -1, np.int64))
+    orc.wake_kick(b, rg, v, 0.5)
+    assert np.array_equal(-b.z[5] / 0.5, [1.0, 1.0, 1.5, 4.0, 6.0, 8.0, 8.0])
+
+
+def test_wake_kick_linear_in_charge(orc):
+    rng = np.random.default_rng(4)
+    z = rng.normal(0, 1e-3, (6, 3000))
+    v = rng.normal(0, 1, 128)
+    rg = np.array([z[4].min(), z[4].max()])
+    out = []
+    for k in (1e-4, 2e-4):
+        b = orc.Beam(z, np.arange(3000, dtype=np.uint32), np.full(3000, -1, np.int64))
+        orc.wake_kick(b, rg, v, k)
+        out.append(b.z[5] - z[5])
+    assert np.allclose(out[1], 2 * out[0], rtol=1e-9, atol=1e-18)
+
+
+# ------------------------------------------------------------------ moments
+def test_moments_vs_fsum(orc):
+    rng = np.random.default_rng(5)
+    z = rng.normal(0, [[1e-3], [1e-4], [1e-3], [1e-4], [1e-3], [1e-3]], (6, 3000))
+    z += np.array([[2e-3], [0], [-1e-3], [0], [5e-2], [1e-3]])
+    lost = np.full(3000, -1, np.int64)
+    lost[5::11] = 1
+    b = orc.Beam(z, np.arange(3000, dtype=np.uint32), lost)
+    m = orc.moments(b)
+    a = z[:, lost < 0]
+    n = a.shape[1]
+    assert m[0] == n
+    mean = [math.fsum(a[k]) / n for k in range(6)]
+    assert np.allclose(m[1:7], mean, rtol=2e-16, atol=0)
+    o = 7
+    for k in range(6):
+        for l in range(k, 6):
+            ref = math.fsum((a[k] - mean[k]) * (a[l] - mean[l])) / n
+            assert m[o] == pytest.approx(ref, rel=1e-14, abs=1e-30)
+            o += 1
+    # population normalisation: the variance of {0, 2} is 1
+    zz = np.zeros((6, 2))
+    zz[0] = [0.0, 2.0]
+    m2 = orc.moments(orc.Beam(zz, np.arange(2, dtype=np.uint32), np.full(2, -1, np.int64)))
+    assert m2[7] == 1.0 and m2[1] == 1.0
+
+
+# ------------------------------------------------------------------ loss reordering
+def test_compaction_order(orc):
+    rng = np.random.default_rng(6)
+    n = 500
+    z = rng.normal(0, 1, (6, n))
+    pid = rng.permutation(n).astype(np.uint32)
+    lost = np.full(n, -1, np.int64)
+    sel = rng.random(n) < 0.3
+    lost[sel] = (rng.integers(0, 4, sel.sum()) << 32) | rng.integers(0, 6, sel.sum())
+    b = orc.Beam(z, pid, lost)
+    nal = orc.compact(b)
+    key = lambda i: (0, 0, i) if lost[i] < 0 else (1, -int(lost[i]), i)
+    order = sorted(range(n), key=key)
+    assert nal == int((lost < 0).sum())
+    assert np.array_equal(b.id, pid[order])
+    assert np.array_equal(b.lost_at, lost[order])
+    assert np.array_equal(b.z, z[:, order])
+
+
+# ------------------------------------------------------------------ driver
+def test_fodo_run_is_thread_count_invariant(orc):
+    lat = inputs.fodo_lattice()
+    d = inputs.gaussian_beam(3000, seed=0)
+    res = []
+    for t in (1, 4):
+        orc.set_threads(t)
+        b = orc.Beam.from_inputs(d)
+        n, mom = orc.track(b, lat, 20, moments=True)
+        res.append((n, b.z.copy(), b.id.copy(), b.lost_at.copy(), mom))
+    orc.set_threads(8)
+    assert res[0][0] == res[1][0]
+    for a, c in zip(res[0][1:], res[1][1:]):
+        assert np.array_equal(a, c)
+
+
+def test_fodo_losses_recorded_and_frozen(orc):
+    lat = inputs.fodo_lattice()
+    d = inputs.gaussian_beam(3000, seed=0, sigmas=(2e-3, 2e-4, 2e-3, 2e-4, 1e-3, 1e-3))
+    b = orc.Beam.from_inputs(d)
+    nal, mom = orc.track(b, lat, 10, moments=True)
+    assert 0 < nal < 3000
+    assert np.all(b.lost_at[:nal] < 0) and np.all(b.lost_at[nal:] >= 0)
+    assert np.all(np.diff(b.lost_at[nal:]) <= 0)            # latest loss first
+    assert np.all(np.diff(b.id[:nal].astype(np.int64)) > 0)  # survivors keep their order
+    # a lost particle's coordinates are those at the exit of the element where
+    # it was lost: re-track it alone up to that element
+    for j in range(nal, min(nal + 20, 3000)):
+        rec = int(b.lost_at[j])
+        p, e = rec >> 32, rec & 0xFFFFFFFF
+        i = int(b.id[j])
+        one = orc.Beam(d["z"][:, i:i + 1], np.array([i], np.uint32), np.array([-1], np.int64))
+        orc.track(one, lat * (p + 1), 1)
+        assert one.lost_at[0] == (0 << 32) | (p * len(lat) + e)
+        assert np.array_equal(one.z[:, 0], b.z[:, j])
+    # moments per pass count survivors
+    assert mom[-1, 0] == nal and np.all(np.diff(mom[:, 0]) <= 0)
+
+
+def test_radiation_kick_stream(orc):
+    """The per-turn energy kick is sigma * g(id, turn); with only the kick in
+    the lattice delta after T turns is the sum of T independent normals."""
+    lat = [Element("RADKICK", sigma=1e-5)]
+    n = 20000
+    z = np.zeros((6, n))
+    b = orc.Beam(z, np.arange(n, dtype=np.uint32), np.full(n, -1, np.int64))
+    orc.track(b, lat, 16, first_pass=3, seed=99)
+    assert b.z[5].std() == pytest.approx(1e-5 * 4.0, rel=0.03)
+    i = 123
+    ref = 0.0
+    for t in range(3, 19):
+        ref += 1e-5 * orc.gauss(i, t, 2, 99)
+    assert b.z[5, i] == pytest.approx(ref, rel=1e-13)
+
+
+def test_bc_histograms_identical_and_compression(orc):
+    """Nothing moves s before the chicane, so every cavity's wake sees the
+    same histogram; the chicane then compresses the chirped bunch."""
+    lat = inputs.bc_lattice(nbins=256)
+    d = inputs.gaussian_beam(20000, seed=1, chirp=inputs.BC_CHIRP)
+    b = orc.Beam.from_inputs(d)
+    s0 = b.z[4].copy()
+    orc.track(b, lat[:-1], 1, p_ref=inputs.BC_P0_EV)
+    assert np.array_equal(b.z[4], s0)
+    sig0 = b.z[4].std()
+    orc.track(b, lat[-1:], 1, p_ref=inputs.BC_P0_EV)
+    assert b.z[4].std() < 0.95 * sig0
