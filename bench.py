@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: particle-element steps per second on one MI355X.
+
+Default workload: the linac bunch compressor -- 4e6 particles of a chirped 6D
+Gaussian beam through 8 zero-length RF cavities, each followed by the
+longitudinal wake step (1024-bin histogram of s, FP32 matrix-core causal
+convolution with a resonator wake, interpolated energy kick), then a
+second-order chicane map (17 elements per pass).  One step = one pass of a
+fresh, already device-resident batch.  A particle-element step is one element
+applied to one particle alive at its entry.
+
+Prints one JSON line with the throughput, the roofline position of the
+dominant kernel (the fused element-run kernel, timed with HIP events on its
+stream during the timed steps) and the CPU oracle timed on a bounded sample.
+
+  python bench.py [--steps K] [--warmup W] [--workload bc|ring|fodo|roof]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# HBM bytes of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a copy kernel of known size); None until measured for
+# the current kernel.
+TRAFFIC_PER_LAUNCH = {}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="bc", choices=["bc", "ring", "fodo", "roof"])
+    ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--particles", type=float, default=None)
+    return ap.parse_args()
+
+
+def run_mask_bytes(lattice, e0, e1, moments=False, next_wake=False):
+    """Algorithmic bytes per particle of one fused launch over elements
+    [e0, e1): each coordinate read by the run is loaded once and each one it
+    changes is stored once (8 B each), the id (4 B) when a random kick needs
+    it, and the 8-byte loss record of particles lost in the run (not counted:
+    data dependent and small)."""
+    rd, wr, need_id = set(), set(), False
+    for e in lattice[e0:e1]:
+        k = e.kind
+        if k == "EDRIFT":
+            rd |= {0, 1, 2, 3, 4}; wr |= {0, 2, 4}
+        elif k in ("QUAD", "MAP2"):
+            c = e.coef if e.coef is not None else None
+            if k == "MAP2":
+                R = c[6:42].reshape(6, 6); T = c[42:].reshape(6, 21)
+                for i in range(6):
+                    ident = c[i] == 0 and R[i, i] == 1 and np.count_nonzero(R[i]) == 1 \
+                        and not T[i].any()
+                    if ident:
+                        continue
+                    wr.add(i)
+                    rd |= set(np.nonzero(R[i])[0].tolist())
+                    pairs = [(j, kk) for j in range(6) for kk in range(j, 6)]
+                    for q in np.nonzero(T[i])[0]:
+                        rd |= set(pairs[q])
+            else:
+                rd |= set(range(6)); wr |= {0, 1, 2, 3, 4}
+        elif k == "MULT":
+            rd |= {0, 1, 2, 3, 5}; wr |= {1, 3}
+        elif k in ("KQUAD", "CSBEND"):
+            rd |= set(range(6)); wr |= {0, 1, 2, 3, 4}
+        elif k in ("RFCA", "WAKE"):
+            rd |= {4, 5}; wr |= {5}
+        elif k == "RADKICK":
+            rd |= {5}; wr |= {5}; need_id = True
+        if e.aperture != "NONE":
+            rd |= {0, 2}
+    if moments:
+        rd |= set(range(6))
+    if next_wake:
+        rd |= {4}
+    rd |= wr
+    return 8 * len(rd) + 8 * len(wr) + (4 if need_id else 0)
+
+
+def launches_of(lattice, passes_per_launch=16, max_e=0):
+    """(e0, e1, npass) of each fused launch, as the library plans them."""
+    n = len(lattice)
+    has_wake = any(e.kind == "WAKE" for e in lattice)
+    if not has_wake and (max_e == 0 or max_e >= n):
+        return [(0, n, passes_per_launch)]
+    out, e0 = [], 0
+    lim = max_e if max_e > 0 else n
+    while e0 < n:
+        e1 = e0 + 1
+        while e1 < n and lattice[e1].kind != "WAKE" and e1 - e0 < lim:
+            e1 += 1
+        out.append((e0, e1, 1))
+        e0 = e1
+    return out
+
+
+def cpu_baseline(lattice, beam_kw, passes, p_ref, sample_n, seed=0):
+    import oracle
+    from paper_1710_07350_amd import inputs
+    d = inputs.gaussian_beam(sample_n, **{k: v for k, v in beam_kw.items() if k != "n"})
+    b = oracle.Beam.from_inputs(d)
+    t0 = time.perf_counter()
+    oracle.track(b, lattice, passes, p_ref=p_ref, seed=seed)
+    dt = time.perf_counter() - t0
+    steps = element_steps(lattice, passes, sample_n, b.lost_at, 0)
+    return steps / dt, dt, oracle.get_threads()
+
+
+def element_steps(lattice, passes, n, lost_at, first_pass):
+    """Exact particle-element steps: survivors traverse every element of every
+    pass; a particle lost at (pass, element) traversed up to that element."""
+    nel = len(lattice)
+    la = np.asarray(lost_at)
+    lost = la[la >= 0]
+    alive = int((la < 0).sum())
+    p = (lost >> 32) - first_pass
+    e = lost & 0xFFFFFFFF
+    return float(alive) * passes * nel + float((p * nel + e + 1).sum())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this "
+              "single-GPU build (the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1710_07350_amd import binding as B
+    from paper_1710_07350_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = args.workload
+    wake_mode = B.WAKE_FP32_MFMA if args.wake_mode == "fp32" else B.WAKE_FP64
+
+    if wl == "bc":
+        lat = inputs.bc_lattice()
+        n = int(args.particles or 4_000_000)
+        beam_kw = dict(n=n, seed=0, chirp=inputs.BC_CHIRP)
+        p_ref, passes_per_step = inputs.BC_P0_EV, 1
+        steps = args.steps or 50
+        warm = args.warmup if args.warmup is not None else 5
+        fresh = True
+        cfg = {"workload": "linac bunch compressor: 4e6-particle chirped Gaussian beam, "
+                           "8 x (RF cavity + 1024-bin wake step) + 2nd-order chicane",
+               "particles": n, "elements_per_pass": len(lat),
+               "wake_convolution": "fp32-mfma" if wake_mode == B.WAKE_FP32_MFMA else "fp64",
+               "batch": "fresh device-resident beam per step"}
+        sample = (n, 10)
+    elif wl == "ring":
+        lat = inputs.ring_lattice(seed=0)
+        n = int(args.particles or 1_000_000)
+        beam_kw = dict(n=n, seed=0)
+        p_ref, passes_per_step = 1e9, 1
+        steps = args.steps or 20
+        warm = args.warmup if args.warmup is not None else 2
+        fresh = False
+        cfg = {"workload": "storage ring: 1e6 particles, 40 cells of Yoshida-4 kick-drift "
+                           "quads and sector bends, random thin sextupoles, Philox radiation "
+                           "kick, elliptical aperture with compaction, moments every turn",
+               "particles": n, "elements_per_pass": len(lat), "turns_per_step": 1}
+        sample = (100_000, 40)
+    else:  # fodo / roof
+        lat = inputs.fodo_lattice()
+        n = int(args.particles or (10_000 if wl == "fodo" else 10_000_000))
+        beam_kw = dict(n=n, seed=0)
+        p_ref = 1e9
+        passes_per_step = 10 if wl == "roof" else 100
+        steps = args.steps or 5
+        warm = args.warmup if args.warmup is not None else 1
+        fresh = True
+        cfg = {"workload": f"FODO channel: {n:.0e} particles, 10 cells (60 elements) per pass, "
+                           f"{passes_per_step} passes per step",
+               "particles": n, "elements_per_pass": len(lat), "fusion_max_elements": args.fusion}
+        sample = (10_000, 100) if wl == "fodo" else (1_000_000, 10)
+
+    L = B.Lattice(lat)
+    d = inputs.gaussian_beam(**beam_kw)
+    template = B.Beam.from_inputs(d)
+    ws = B.Workspace(n)
+    nb = (warm + steps) if fresh else 1
+    beams = []
+    for _ in range(nb):
+        b = B.Beam.__new__(B.Beam)
+        b.n = n
+        b.z = template.z.clone()
+        b.id = template.id.clone()
+        b.lost_at = template.lost_at.clone()
+        b.n_alive = template.n_alive.clone()
+        beams.append(b)
+    mom = torch.zeros((max(passes_per_step, 1), 28), dtype=torch.float64, device="cuda")
+    use_mom = wl == "ring"
+    stream = torch.cuda.current_stream()
+
+    def one_step(i):
+        b = beams[i if fresh else 0]
+        fp = 0 if fresh else i * passes_per_step
+        B.track(b, L, passes_per_step, ws, seed=7, first_pass=fp, p_ref=p_ref,
+                moments=mom if use_mom else None, wake_mode=wake_mode,
+                max_elems_per_launch=args.fusion, stream=stream)
+
+    for i in range(warm):
+        one_step(i)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(warm, warm + steps):
+        one_step(i)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    run_ms, run_launches = B.profile_read(0)
+    B.profile_enable(False)
+
+    # exact particle-element steps of the timed region
+    if fresh:
+        total_steps = 0.0
+        for i in range(warm, warm + steps):
+            la = beams[i].lost_at.cpu().numpy()
+            total_steps += element_steps(lat, passes_per_step, n, la, 0)
+    else:
+        # a continuing beam: count survivors per turn from the loss records
+        la = beams[0].lost_at.cpu().numpy()
+        first = warm * passes_per_step
+        last = (warm + steps) * passes_per_step
+        nel = len(lat)
+        lp = la >> 32
+        total_steps = 0.0
+        alive_end = float((la < 0).sum())
+        lost = la >= 0
+        after = lost & (lp >= last)
+        total_steps += (alive_end + float(after.sum())) * (last - first) * nel
+        inside = lost & (lp >= first) & (lp < last)
+        pl = lp[inside] - first
+        el = la[inside] & 0xFFFFFFFF
+        total_steps += float((pl * nel + el + 1).sum())
+    value = total_steps / (ms_total / 1e3)
+
+    # roofline of the dominant kernel (fused element run)
+    plan = launches_of(lat, 16, args.fusion)
+    bytes_per_pass = 0.0
+    launches_per_pass = 0.0
+    for j, (e0, e1, npass) in enumerate(plan):
+        nxt = plan[(j + 1) % len(plan)][0] if len(plan) > 1 else None
+        next_wake = nxt is not None and lat[nxt].kind == "WAKE" and (j + 1 < len(plan))
+        per = run_mask_bytes(lat, e0, e1, moments=(use_mom and e1 == len(lat)),
+                             next_wake=next_wake)
+        if npass > 1:
+            bytes_per_pass += per / npass
+            launches_per_pass += 1.0 / npass
+        else:
+            bytes_per_pass += per
+            launches_per_pass += 1.0
+    alive_mean = total_steps / (steps * passes_per_step * len(lat))
+    alg_bytes_per_launch = alive_mean * bytes_per_pass / launches_per_pass
+    avg_ms = run_ms / max(run_launches, 1)
+    achieved = alg_bytes_per_launch / (avg_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": "trk::k_run (fused element run)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC_PER_LAUNCH.get(wl),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
+            "alg_bytes_per_launch": round(alg_bytes_per_launch)}
+
+    out = {"metric": "particle·element steps/s (FP64 tracking)", "value": value,
+           "unit": "particle·element steps/s", "n_gpus": 1, "steps": steps,
+           "warmup": warm, "ms_per_step": ms_total / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": cfg, "roofline": roof}
+    if not args.no_cpu_baseline:
+        sn, sp = sample
+        cv, cdt, cores = cpu_baseline(lat, beam_kw, sp, p_ref, sn)
+        out["cpu_baseline"] = {"value": cv, "unit": "particle·element steps/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"{sn} particles of the same workload, {sp} passes, "
+                                         f"{cdt:.1f} s wall"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -286,23 +286,38 @@ static void edrift(double *z, double L) {
 }
 
 /* Second-order map in TRANSPORT form: every output from the input vector,
- * z_i = C_i + sum_j R_ij z_j + sum_{j<=k} T_ijk z_j z_k, coefficients equal to
- * zero skipped, order C, R by ascending j, T by ascending (j,k). */
+ * z_i = C_i + sum_j R_ij z_j + sum_{j<=k} T_ijk z_j z_k, a plain left-to-right
+ * sum over the non-zero terms in the order C, R by ascending j, T by
+ * ascending (j,k): the first term is the sum so far (a product of a
+ * coefficient and the coordinates), each later term is added with one fma.
+ * A row without terms yields 0; a row whose only term is R_ii = 1 is an
+ * exact identity. */
 static void map2(double *z, const double *coef) {
   double in[6], out[6];
   memcpy(in, z, sizeof in);
   for (int i = 0; i < 6; ++i) {
     double acc = 0.0;
-    if (coef[i] != 0.0) acc = acc + coef[i];
+    int have = 0;
+    if (coef[i] != 0.0) {
+      acc = coef[i];
+      have = 1;
+    }
     for (int j = 0; j < 6; ++j) {
       double r = coef[6 + i * 6 + j];
-      if (r != 0.0) acc = fma(r, in[j], acc);
+      if (r != 0.0) {
+        acc = have ? fma(r, in[j], acc) : r * in[j];
+        have = 1;
+      }
     }
     int p = 0;
     for (int j = 0; j < 6; ++j)
       for (int k = j; k < 6; ++k, ++p) {
         double t = coef[42 + i * 21 + p];
-        if (t != 0.0) acc = fma(t, in[j] * in[k], acc);
+        if (t != 0.0) {
+          double m = in[j] * in[k];
+          acc = have ? fma(t, m, acc) : t * m;
+          have = 1;
+        }
       }
     out[i] = acc;
   }

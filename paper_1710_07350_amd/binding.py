@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libtrk.so (include/trk.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the computation runs in the library's kernels.  The
+binding refuses to run when the library is missing -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrk.so")
+
+TRK_OK, TRK_EINVAL, TRK_EPTR, TRK_EHIP, TRK_ENOMEM, TRK_ERANGE = 0, -1, -2, -3, -4, -5
+KIND = {"EDRIFT": 1, "QUAD": 2, "MAP2": 3, "MULT": 4, "KQUAD": 5, "CSBEND": 6,
+        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10}
+APER = {"NONE": 0, "RECT": 1, "ELLIPSE": 2}
+WAKE_FP64, WAKE_FP32_MFMA = 0, 1
+MAX_BINS = 4096
+
+# symbols declared in include/trk.h
+EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
+           "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_moments",
+           "trk_compact_lost", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
+           "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read")
+
+
+class TrkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"trk error {status}: {msg}")
+        self.status = status
+
+
+class Element(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("aperture", C.c_int32), ("order", C.c_int32),
+                ("nsteps", C.c_int32), ("nbins", C.c_int32), ("reserved", C.c_int32),
+                ("L", C.c_double), ("k", C.c_double), ("angle", C.c_double),
+                ("volt", C.c_double), ("phase", C.c_double), ("freq", C.c_double),
+                ("wake_A", C.c_double), ("wake_tau0", C.c_double), ("wake_omega", C.c_double),
+                ("charge", C.c_double), ("sigma", C.c_double), ("ax", C.c_double),
+                ("ay", C.c_double), ("coef", C.POINTER(C.c_double))]
+
+
+class BeamStruct(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("xp", C.c_void_p), ("y", C.c_void_p), ("yp", C.c_void_p),
+                ("s", C.c_void_p), ("dp", C.c_void_p), ("id", C.c_void_p),
+                ("lost_at", C.c_void_p), ("n_alive", C.c_void_p), ("n_total", C.c_int64)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("first_pass", C.c_int32),
+                ("passes_per_launch", C.c_int32), ("max_elems_per_launch", C.c_int32),
+                ("wake_mode", C.c_int32), ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+                ("p_ref_eV", C.c_double), ("moments", C.c_void_p)]
+
+
+class Wake(C.Structure):
+    _fields_ = [("A", C.c_double), ("tau0", C.c_double), ("omega", C.c_double),
+                ("charge", C.c_double)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libtrk.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first "
+                               "(there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64, d, sz = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32,
+                                         C.c_uint64, C.c_double, C.c_size_t)
+        L.trk_lattice_create.argtypes = [C.POINTER(Element), i32, C.POINTER(vp)]
+        L.trk_lattice_destroy.argtypes = [vp]
+        L.trk_lattice_destroy.restype = None
+        L.trk_workspace_size.argtypes = [vp, i64]
+        L.trk_workspace_size.restype = sz
+        L.trk_track.argtypes = [C.POINTER(BeamStruct), vp, i32, C.POINTER(Opts), vp, sz, vp]
+        L.trk_histogram.argtypes = [C.POINTER(BeamStruct), i32, vp, vp, vp, sz, vp]
+        L.trk_wake_convolve.argtypes = [vp, i32, vp, d, d, i32, vp, vp]
+        L.trk_wake_kick.argtypes = [C.POINTER(BeamStruct), vp, i32, vp, C.POINTER(Wake), d, i32,
+                                    vp, sz, vp]
+        L.trk_moments.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
+        L.trk_compact_lost.argtypes = [C.POINTER(BeamStruct), vp, sz, vp]
+        L.trk_elementary.argtypes = [i32, vp, vp, vp, i64, vp]
+        L.trk_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
+        L.trk_gauss.argtypes = [vp, u32, u32, u64, vp, i64, vp]
+        L.trk_status_string.argtypes = [C.c_int]
+        L.trk_status_string.restype = C.c_char_p
+        L.trk_last_error.restype = C.c_char_p
+        L.trk_profile_enable.argtypes = [i32]
+        L.trk_profile_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int) -> None:
+    if status != TRK_OK:
+        raise TrkError(status, lib().trk_last_error().decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------ lattice
+class Lattice:
+    """Device copy of a lattice (a list of inputs.Element descriptions)."""
+
+    def __init__(self, elements):
+        self.elements = list(elements)
+        arr = (Element * max(1, len(self.elements)))()
+        keep = []
+        for i, e in enumerate(self.elements):
+            r = arr[i]
+            r.kind = KIND[e.kind]
+            r.aperture = APER[e.aperture]
+            r.order, r.nsteps, r.nbins = e.order, e.nsteps, e.nbins
+            r.L, r.k, r.angle = e.L, e.k, e.angle
+            r.volt, r.phase, r.freq = e.volt, e.phase, e.freq
+            r.wake_A, r.wake_tau0, r.wake_omega, r.charge = (e.wake_A, e.wake_tau0,
+                                                             e.wake_omega, e.charge)
+            r.sigma, r.ax, r.ay = e.sigma, e.ax, e.ay
+            if e.coef is not None:
+                c = np.ascontiguousarray(e.coef, dtype=np.float64)
+                keep.append(c)
+                r.coef = c.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        _check(lib().trk_lattice_create(arr, len(self.elements), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.trk_lattice_destroy(h)
+            self.handle = None
+
+
+# ------------------------------------------------------------------ beam
+class Beam:
+    """Device beam held in torch tensors: z [6, n] float64 (rows are the SoA
+    coordinate arrays), id uint32 (as int32 storage), lost_at int64, n_alive."""
+
+    def __init__(self, z, pid, lost_at, n_alive: Optional[int] = None, device="cuda"):
+        import torch
+        z = torch.as_tensor(np.ascontiguousarray(z), dtype=torch.float64)
+        self.n = int(z.shape[1])
+        self.z = z.to(device).contiguous()
+        pid = np.ascontiguousarray(pid, dtype=np.uint32).view(np.int32)
+        self.id = torch.as_tensor(pid).to(device).contiguous()
+        self.lost_at = torch.as_tensor(np.ascontiguousarray(lost_at, dtype=np.int64)).to(device)
+        na = self.n if n_alive is None else int(n_alive)
+        self.n_alive = torch.tensor([na], dtype=torch.int64, device=device)
+        self._struct = None
+
+    @classmethod
+    def from_inputs(cls, d: dict, device="cuda") -> "Beam":
+        return cls(d["z"], d["id"], d["lost_at"], device=device)
+
+    def struct(self) -> BeamStruct:
+        b = BeamStruct()
+        zp = [self.z[k].data_ptr() for k in range(6)]
+        b.x, b.xp, b.y, b.yp, b.s, b.dp = zp
+        b.id = _ptr(self.id)
+        b.lost_at = _ptr(self.lost_at)
+        b.n_alive = _ptr(self.n_alive)
+        b.n_total = self.n
+        self._struct = b
+        return b
+
+    def host(self) -> dict:
+        """Copy back (synchronises): z, id (uint32), lost_at, n_alive."""
+        return {"z": self.z.cpu().numpy(), "id": self.id.cpu().numpy().view(np.uint32),
+                "lost_at": self.lost_at.cpu().numpy(), "n_alive": int(self.n_alive.item())}
+
+
+class Workspace:
+    def __init__(self, n_total: int, lattice: Optional[Lattice] = None, device="cuda"):
+        import torch
+        nbytes = int(lib().trk_workspace_size(lattice.handle if lattice else None, n_total))
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+# ------------------------------------------------------------------ calls
+def track(beam: Beam, lattice: Lattice, passes: int, ws: Workspace, seed: int = 0,
+          first_pass: int = 0, p_ref: float = 1e9, moments=None, wake_mode: int = WAKE_FP64,
+          passes_per_launch: int = 0, max_elems_per_launch: int = 0, stream=None) -> None:
+    o = Opts()
+    o.seed = seed
+    o.first_pass = first_pass
+    o.passes_per_launch = passes_per_launch
+    o.max_elems_per_launch = max_elems_per_launch
+    o.wake_mode = wake_mode
+    o.p_ref_eV = p_ref
+    o.moments = moments.data_ptr() if moments is not None else None
+    _check(lib().trk_track(C.byref(beam.struct()), lattice.handle, passes, C.byref(o), ws.ptr,
+                           ws.nbytes, _stream_handle(stream)))
+
+
+def histogram(beam: Beam, nbins: int, ws: Workspace, stream=None):
+    import torch
+    rng = torch.empty(2, dtype=torch.float64, device=beam.z.device)
+    cnt = torch.empty(nbins, dtype=torch.int32, device=beam.z.device)
+    _check(lib().trk_histogram(C.byref(beam.struct()), nbins, rng.data_ptr(), cnt.data_ptr(),
+                               ws.ptr, ws.nbytes, _stream_handle(stream)))
+    return rng, cnt
+
+
+def wake_convolve(counts, nbins: int, rng, tau0: float, omega: float, mode: int, stream=None):
+    import torch
+    v = torch.empty(nbins, dtype=torch.float64, device=rng.device)
+    _check(lib().trk_wake_convolve(counts.data_ptr(), nbins, rng.data_ptr(), tau0, omega, mode,
+                                   v.data_ptr(), _stream_handle(stream)))
+    return v
+
+
+def wake_kick(beam: Beam, counts, nbins: int, rng, A: float, tau0: float, omega: float,
+              charge: float, p_ref: float, mode: int, ws: Workspace, stream=None) -> None:
+    w = Wake(A, tau0, omega, charge)
+    _check(lib().trk_wake_kick(C.byref(beam.struct()), counts.data_ptr(), nbins, rng.data_ptr(),
+                               C.byref(w), p_ref, mode, ws.ptr, ws.nbytes, _stream_handle(stream)))
+
+
+def moments(beam: Beam, ws: Workspace, stream=None):
+    import torch
+    out = torch.empty(28, dtype=torch.float64, device=beam.z.device)
+    _check(lib().trk_moments(C.byref(beam.struct()), out.data_ptr(), ws.ptr, ws.nbytes,
+                             _stream_handle(stream)))
+    return out
+
+
+def compact_lost(beam: Beam, ws: Workspace, stream=None) -> None:
+    _check(lib().trk_compact_lost(C.byref(beam.struct()), ws.ptr, ws.nbytes,
+                                  _stream_handle(stream)))
+
+
+def elementary(fn: int, x, y=None, stream=None):
+    import torch
+    out = torch.empty_like(x)
+    _check(lib().trk_elementary(fn, x.data_ptr(), y.data_ptr() if y is not None else None,
+                                out.data_ptr(), x.numel(), _stream_handle(stream)))
+    return out
+
+
+def philox(ctr, key, stream=None):
+    import torch
+    n = ctr.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
+    _check(lib().trk_philox4x32_10(ctr.data_ptr(), key.data_ptr(), out.data_ptr(), n,
+                                   _stream_handle(stream)))
+    return out
+
+
+def gauss(pid, step: int, tag: int, seed: int, stream=None):
+    import torch
+    out = torch.empty(pid.shape[0], dtype=torch.float64, device=pid.device)
+    _check(lib().trk_gauss(pid.data_ptr(), step, tag, seed, out.data_ptr(), pid.shape[0],
+                           _stream_handle(stream)))
+    return out
+
+
+def profile_enable(on: bool) -> None:
+    _check(lib().trk_profile_enable(1 if on else 0))
+
+
+def profile_read(cls: int = 0):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().trk_profile_read(cls, C.byref(ms), C.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,864 @@
+// api.cpp -- host side of the C-ABI (include/trk.h): argument checks, lattice
+// compilation (element classification and per-element constants), launch
+// planning and sequencing.  Every step of the tracking runs in the kernels of
+// the .hip translation units; nothing here touches particle data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "trk_internal.h"
+
+using namespace trk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const std::string &msg) {
+  g_err = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(TRK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// A pointer is accepted as "device" if the runtime knows it as device or
+// managed memory; plain host memory is rejected before any launch.
+int check_dev(const void *p, const char *name) {
+  if (p == nullptr) return fail(TRK_EINVAL, std::string(name) + " is NULL");
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TRK_EPTR, std::string(name) + " is not a device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(TRK_EPTR, std::string(name) + " is not a device pointer");
+  return TRK_OK;
+}
+
+int check_beam(const trk_beam *b) {
+  if (b == nullptr) return fail(TRK_EINVAL, "beam is NULL");
+  if (b->n_total < 0 || b->n_total > 0xffffffffLL)
+    return fail(TRK_ERANGE, "n_total must lie in [0, 2^32)");
+  const void *ptrs[9] = {b->x, b->xp, b->y, b->yp, b->s, b->dp, b->id, b->lost_at, b->n_alive};
+  const char *names[9] = {"beam.x", "beam.xp", "beam.y", "beam.yp", "beam.s",
+                          "beam.dp", "beam.id", "beam.lost_at", "beam.n_alive"};
+  for (int k = 0; k < 9; ++k) {
+    int r = check_dev(ptrs[k], names[k]);
+    if (r) return r;
+  }
+  return TRK_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+  double ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+} g_prof;
+
+template <class F>
+hipError_t profiled(int cls, hipStream_t st, F &&launch) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    on = g_prof.on;
+  }
+  if (!on) return launch();
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&b);
+  if (e != hipSuccess) return e;
+  (void)hipEventRecord(a, st);
+  e = launch();
+  (void)hipEventRecord(b, st);
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.ev[cls].push_back({a, b});
+  return e;
+}
+
+// ------------------------------------------------------------------ constants
+// Fourth-order symmetric composition (Yoshida 1990): kicks c, drifts d.
+void yoshida(double c[4], double d[3]) {
+  const double cr = std::cbrt(2.0);
+  const double w1 = 1.0 / (2.0 - cr);
+  const double w0 = -cr / (2.0 - cr);
+  c[0] = 0.5 * w1;
+  c[1] = 0.5 * (w0 + w1);
+  c[2] = 0.5 * (w0 + w1);
+  c[3] = 0.5 * w1;
+  d[0] = w1;
+  d[1] = w0;
+  d[2] = w1;
+}
+
+int pair_index(int j, int k) {  // (j,k), j<=k, among the 21 monomials
+  return j * 6 - j * (j - 1) / 2 + (k - j);
+}
+
+// Thick quadrupole, second order: paraxial x'' = -K x, y'' = K y with
+// K = k1/(1+delta).  First order cos/sin (cosh/sinh); T_ij6 = dR_ij/ddelta;
+// T_5jk from the path integral of (x'^2 + y'^2)/2 along the linear orbit.
+void quad_coef(double L, double k1, double c[168]) {
+  std::memset(c, 0, 168 * sizeof(double));
+  double *R = c + 6, *T = c + 42;
+  R[4 * 6 + 4] = 1.0;
+  R[5 * 6 + 5] = 1.0;
+  if (k1 == 0.0) {
+    R[0] = 1.0; R[1] = L; R[7] = 1.0;
+    R[14] = 1.0; R[15] = L; R[21] = 1.0;
+    T[4 * 21 + pair_index(1, 1)] = 0.5 * L;
+    T[4 * 21 + pair_index(3, 3)] = 0.5 * L;
+    return;
+  }
+  const double w = std::sqrt(std::fabs(k1));
+  const double phi = w * L;
+  const double cf = std::cos(phi), sf = std::sin(phi), s2f = std::sin(2.0 * phi);
+  const double ch = std::cosh(phi), sh = std::sinh(phi), sh2 = std::sinh(2.0 * phi);
+  // plane blocks: R (11 12 21 22), T (16 26 for row 1, 16 26 for row 2), S (11 12 22)
+  const double foc_R[4] = {cf, sf / w, -w * sf, cf};
+  const double foc_T[4] = {(0.5 * phi) * sf, (sf - phi * cf) / (2.0 * w),
+                           (0.5 * w) * (sf + phi * cf), (0.5 * phi) * sf};
+  const double foc_S[3] = {(0.5 * (w * w)) * (0.5 * L - s2f / (4.0 * w)), -0.5 * (sf * sf),
+                           0.5 * (0.5 * L + s2f / (4.0 * w))};
+  const double def_R[4] = {ch, sh / w, w * sh, ch};
+  const double def_T[4] = {-((0.5 * phi) * sh), (sh - phi * ch) / (2.0 * w),
+                           -((0.5 * w) * (sh + phi * ch)), -((0.5 * phi) * sh)};
+  const double def_S[3] = {(0.5 * (w * w)) * (sh2 / (4.0 * w) - 0.5 * L), 0.5 * (sh * sh),
+                           0.5 * (0.5 * L + sh2 / (4.0 * w))};
+  for (int plane = 0; plane < 2; ++plane) {
+    const bool focusing = (plane == 0) == (k1 > 0.0);
+    const double *pr = focusing ? foc_R : def_R;
+    const double *pt = focusing ? foc_T : def_T;
+    const double *ps = focusing ? foc_S : def_S;
+    const int o = 2 * plane;
+    R[(o + 0) * 6 + (o + 0)] = pr[0];
+    R[(o + 0) * 6 + (o + 1)] = pr[1];
+    R[(o + 1) * 6 + (o + 0)] = pr[2];
+    R[(o + 1) * 6 + (o + 1)] = pr[3];
+    T[(o + 0) * 21 + pair_index(o, 5)] = pt[0];
+    T[(o + 0) * 21 + pair_index(o + 1, 5)] = pt[1];
+    T[(o + 1) * 21 + pair_index(o, 5)] = pt[2];
+    T[(o + 1) * 21 + pair_index(o + 1, 5)] = pt[3];
+    T[4 * 21 + pair_index(o, o)] = ps[0];
+    T[4 * 21 + pair_index(o, o + 1)] = ps[1];
+    T[4 * 21 + pair_index(o + 1, o + 1)] = ps[2];
+  }
+}
+
+// classification of a 168-coefficient map by its exact non-zero set
+struct Term {
+  int i, j, k;  // k < 0: an R term
+};
+const Term kP1[24] = {{0, 0, -1}, {0, 1, -1}, {0, 0, 5}, {0, 1, 5}, {1, 0, -1}, {1, 1, -1},
+                      {1, 0, 5},  {1, 1, 5},  {2, 2, -1}, {2, 3, -1}, {2, 2, 5}, {2, 3, 5},
+                      {3, 2, -1}, {3, 3, -1}, {3, 2, 5}, {3, 3, 5},  {4, 4, -1}, {4, 0, 0},
+                      {4, 0, 1},  {4, 1, 1},  {4, 2, 2}, {4, 2, 3},  {4, 3, 3},  {5, 5, -1}};
+const Term kP2[8] = {{0, 0, -1}, {1, 1, -1}, {2, 2, -1}, {3, 3, -1},
+                     {4, 4, -1}, {4, 5, -1}, {5, 5, -1}, {4, 5, 5}};
+
+int coef_index(const Term &t) {
+  return t.k < 0 ? 6 + 6 * t.i + t.j : 42 + 21 * t.i + pair_index(t.j, t.k);
+}
+
+bool matches(const double *c, const Term *pat, int n, std::vector<double> &out) {
+  std::vector<char> in_pat(168, 0);
+  for (int q = 0; q < n; ++q) in_pat[coef_index(pat[q])] = 1;
+  for (int q = 0; q < 168; ++q) {
+    const bool nz = c[q] != 0.0;
+    if (nz != static_cast<bool>(in_pat[q])) return false;
+  }
+  out.clear();
+  for (int q = 0; q < n; ++q) out.push_back(c[coef_index(pat[q])]);
+  return true;
+}
+
+constexpr uint32_t M_X = 1, M_XP = 2, M_Y = 4, M_YP = 8, M_S = 16, M_DP = 32, M_ID = 64;
+constexpr uint32_t M_ALL = 63;
+
+}  // namespace
+
+// ------------------------------------------------------------------ lattice
+struct trk_lattice {
+  std::vector<DevElem> rec;
+  std::vector<double> pool;
+  std::vector<trk_element> src;
+  std::vector<uint32_t> rd, wr;   // per element coordinate masks
+  std::vector<char> aper;         // element has an aperture
+  std::vector<int> vslot;         // -1 or ordinal among pass-varying elements
+  int nvar = 0;
+  bool has_wake = false;
+  int max_bins = 0;
+  DevElem *d_rec = nullptr;
+  double *d_pool = nullptr;
+};
+
+extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_lattice **out) {
+  if (out == nullptr) return fail(TRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || n > TRK_MAX_ELEMENTS) return fail(TRK_ERANGE, "element count out of range");
+  if (n > 0 && elems == nullptr) return fail(TRK_EINVAL, "elems is NULL");
+  trk_lattice *L = new (std::nothrow) trk_lattice();
+  if (L == nullptr) return fail(TRK_ENOMEM, "host allocation failed");
+  double yc[4], yd[3];
+  yoshida(yc, yd);
+  for (int e = 0; e < n; ++e) {
+    const trk_element &s = elems[e];
+    DevElem d;
+    std::memset(&d, 0, sizeof d);
+    d.vslot = -1;
+    d.off = static_cast<int32_t>(L->pool.size());
+    uint32_t rd = 0, wr = 0;
+    auto bad = [&](const char *why) {
+      delete L;
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "element %d: %s", e, why);
+      return fail(TRK_EINVAL, buf);
+    };
+    switch (s.kind) {
+      case TRK_EDRIFT:
+        d.kind = K_EDRIFT;
+        d.p0 = s.L;
+        rd = M_X | M_XP | M_Y | M_YP | M_S;
+        wr = M_X | M_Y | M_S;
+        break;
+      case TRK_QUAD:
+      case TRK_MAP2: {
+        double c[168];
+        if (s.kind == TRK_QUAD) {
+          if (!(s.L > 0.0)) return bad("QUAD needs L > 0");
+          quad_coef(s.L, s.k, c);
+        } else {
+          if (s.coef == nullptr) return bad("MAP2 needs coef");
+          std::memcpy(c, s.coef, sizeof c);
+        }
+        std::vector<double> v;
+        if (matches(c, kP1, 24, v)) {
+          d.kind = K_MAP2_P1;
+        } else if (matches(c, kP2, 8, v)) {
+          d.kind = K_MAP2_P2;
+        } else {
+          d.kind = K_MAP2_GEN;
+          v.assign(c, c + 168);
+        }
+        L->pool.insert(L->pool.end(), v.begin(), v.end());
+        // rows that are exact identities (only R_ii = 1) neither read nor write
+        for (int i = 0; i < 6; ++i) {
+          bool ident = c[6 + 7 * i] == 1.0 && c[i] == 0.0;
+          for (int q = 0; q < 6 && ident; ++q)
+            if (q != i && c[6 + 6 * i + q] != 0.0) ident = false;
+          for (int q = 0; q < 21 && ident; ++q)
+            if (c[42 + 21 * i + q] != 0.0) ident = false;
+          if (ident) continue;
+          wr |= 1u << i;
+          for (int j = 0; j < 6; ++j)
+            if (c[6 + 6 * i + j] != 0.0) rd |= 1u << j;
+          int q = 0;
+          for (int j = 0; j < 6; ++j)
+            for (int k = j; k < 6; ++k, ++q)
+              if (c[42 + 21 * i + q] != 0.0) rd |= (1u << j) | (1u << k);
+        }
+        break;
+      }
+      case TRK_MULT: {
+        if (s.order < 1 || s.order > 8) return bad("MULT order must be 1..8");
+        double f = 1.0;
+        for (int i = 2; i <= s.order; ++i) f *= static_cast<double>(i);
+        d.kind = K_MULT;
+        d.ip = s.order;
+        d.p0 = s.k / f;
+        rd = M_X | M_XP | M_Y | M_YP | M_DP;
+        wr = M_XP | M_YP;
+        break;
+      }
+      case TRK_KQUAD:
+      case TRK_CSBEND: {
+        if (s.nsteps < 1 || s.nsteps > 4096) return bad("nsteps must be 1..4096");
+        if (s.L == 0.0) return bad("kick-drift element needs L != 0");
+        const double ls = s.L / static_cast<double>(s.nsteps);
+        double dl[3];
+        for (int i = 0; i < 3; ++i) dl[i] = yd[i] * ls;
+        d.ip = s.nsteps;
+        if (s.kind == TRK_KQUAD) {
+          d.kind = K_KQUAD;
+          for (int i = 0; i < 4; ++i) L->pool.push_back((yc[i] * ls) * s.k);
+          for (int i = 0; i < 3; ++i) L->pool.push_back(dl[i]);
+        } else {
+          if (s.angle == 0.0) return bad("CSBEND needs angle != 0");
+          d.kind = K_CSBEND;
+          const double h = s.angle / s.L;
+          const double rho = s.L / s.angle;
+          double kA[4], kB[4];
+          for (int i = 0; i < 4; ++i) {
+            kA[i] = (yc[i] * ls) * h;
+            kB[i] = kA[i] * h;
+          }
+          double cph[3], sph[3], vers[3], rs[3];
+          for (int i = 0; i < 3; ++i) {
+            const double phi = dl[i] * h;
+            const double shalf = std::sin(0.5 * phi);
+            cph[i] = std::cos(phi);
+            sph[i] = std::sin(phi);
+            vers[i] = 2.0 * rho * (shalf * shalf);
+            rs[i] = rho * sph[i];
+          }
+          L->pool.insert(L->pool.end(), kA, kA + 4);
+          L->pool.insert(L->pool.end(), kB, kB + 4);
+          L->pool.insert(L->pool.end(), cph, cph + 3);
+          L->pool.insert(L->pool.end(), sph, sph + 3);
+          L->pool.insert(L->pool.end(), vers, vers + 3);
+          L->pool.insert(L->pool.end(), rs, rs + 3);
+          L->pool.insert(L->pool.end(), dl, dl + 3);
+        }
+        rd = M_ALL;
+        wr = M_X | M_XP | M_Y | M_YP | M_S;
+        break;
+      }
+      case TRK_RFCA: {
+        constexpr double kTwoPi = 0x1.921fb54442d18p+2;
+        d.kind = K_RFCA;
+        d.p0 = 0.5 * ((kTwoPi * s.freq) / 299792458.0);
+        d.p1 = s.phase;
+        d.p2 = s.volt;
+        d.vslot = L->nvar++;
+        rd = M_S | M_DP;
+        wr = M_DP;
+        break;
+      }
+      case TRK_WAKE:
+        if (s.nbins < 2 || s.nbins > TRK_MAX_BINS) return bad("WAKE nbins must be 2..TRK_MAX_BINS");
+        if (!(s.wake_tau0 > 0.0)) return bad("WAKE needs tau0 > 0");
+        d.kind = K_WAKE;
+        d.ip = s.nbins;
+        d.vslot = L->nvar++;
+        L->has_wake = true;
+        L->max_bins = std::max(L->max_bins, s.nbins);
+        rd = M_S | M_DP;
+        wr = M_DP;
+        break;
+      case TRK_RADKICK:
+        d.kind = K_RADKICK;
+        d.p0 = s.sigma;
+        rd = M_DP | M_ID;
+        wr = M_DP;
+        break;
+      case TRK_MARKER:
+        d.kind = K_MARKER;
+        break;
+      default:
+        return bad("unknown element kind");
+    }
+    d.aper = s.aperture;
+    if (s.aperture == TRK_APER_RECT) {
+      if (!(s.ax > 0.0 && s.ay > 0.0)) return bad("aperture needs ax, ay > 0");
+      d.a0 = s.ax;
+      d.a1 = s.ay;
+      rd |= M_X | M_Y;
+    } else if (s.aperture == TRK_APER_ELLIPSE) {
+      if (!(s.ax > 0.0 && s.ay > 0.0)) return bad("aperture needs ax, ay > 0");
+      d.a0 = 1.0 / s.ax;
+      d.a1 = 1.0 / s.ay;
+      rd |= M_X | M_Y;
+    } else if (s.aperture != TRK_APER_NONE) {
+      return bad("unknown aperture");
+    }
+    L->rec.push_back(d);
+    trk_element cp = s;
+    cp.coef = nullptr;
+    L->src.push_back(cp);
+    L->rd.push_back(rd);
+    L->wr.push_back(wr);
+    L->aper.push_back(s.aperture != TRK_APER_NONE);
+    L->vslot.push_back(d.vslot);
+  }
+  if (L->pool.empty()) L->pool.push_back(0.0);
+  size_t rb = std::max<size_t>(1, L->rec.size()) * sizeof(DevElem);
+  hipError_t e = hipMalloc(&L->d_rec, rb);
+  if (e == hipSuccess) e = hipMalloc(&L->d_pool, L->pool.size() * sizeof(double));
+  if (e == hipSuccess && !L->rec.empty())
+    e = hipMemcpy(L->d_rec, L->rec.data(), L->rec.size() * sizeof(DevElem), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(L->d_pool, L->pool.data(), L->pool.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(L->d_rec);
+    (void)hipFree(L->d_pool);
+    delete L;
+    return fail(e == hipErrorOutOfMemory ? TRK_ENOMEM : TRK_EHIP,
+                std::string("lattice upload: ") + hipGetErrorString(e));
+  }
+  *out = L;
+  return TRK_OK;
+}
+
+extern "C" void trk_lattice_destroy(trk_lattice *lat) {
+  if (lat == nullptr) return;
+  (void)hipFree(lat->d_rec);
+  (void)hipFree(lat->d_pool);
+  delete lat;
+}
+
+// ------------------------------------------------------------------ workspace
+namespace trk {
+
+constexpr int kMomPassesMax = 16;
+
+namespace {
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+Workspace carve(void *base, int64_t n_total, size_t *bytes) {
+  const size_t n = static_cast<size_t>(std::max<int64_t>(n_total, 1));
+  const size_t nb = static_cast<size_t>(std::max<int64_t>(nblocks(n_total), 1));
+  Carver c{static_cast<char *>(base)};
+  Workspace w;
+  w.mm_part = c.take<double>(2 * std::max<size_t>(nb, kMaxGridStride));
+  w.counts = c.take<uint32_t>(TRK_MAX_BINS);
+  w.range = c.take<double>(2);
+  w.wake_par = c.take<double>(2);
+  w.wake_v = c.take<double>(TRK_MAX_BINS);
+  w.mom_shift = c.take<double>(6);
+  w.mom_tmp = c.take<double>(28);
+  w.mom_part = c.take<double>(static_cast<size_t>(kMomPassesMax) * std::max<size_t>(nb, 1024) * 28);
+  w.cmp_blk = c.take<int64_t>(nb * 10);
+  w.cmp_hdr = c.take<int64_t>(16);
+  w.key_a = c.take<uint64_t>(n);
+  w.key_b = c.take<uint64_t>(n);
+  w.pos_a = c.take<uint32_t>(n);
+  w.pos_b = c.take<uint32_t>(n);
+  for (int k = 0; k < 6; ++k) w.tz[k] = c.take<double>(n);
+  w.tid = c.take<uint32_t>(n);
+  w.tlost = c.take<int64_t>(n);
+  if (bytes) *bytes = c.off + 256;
+  return w;
+}
+}  // namespace
+
+size_t workspace_bytes(int64_t n_total) {
+  size_t b = 0;
+  carve(nullptr, n_total, &b);
+  return b;
+}
+Workspace carve_workspace(void *base, int64_t n_total) { return carve(base, n_total, nullptr); }
+
+}  // namespace trk
+
+extern "C" size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total) {
+  (void)lat;
+  return workspace_bytes(n_total);
+}
+
+namespace {
+
+int check_ws(void *ws, size_t bytes, int64_t n_total) {
+  const size_t need = workspace_bytes(n_total);
+  if (bytes < need) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", bytes, need);
+    return fail(TRK_ERANGE, buf);
+  }
+  return check_dev(ws, "workspace");
+}
+
+void beam_ptrs(const trk_beam *b, double *z[6]) {
+  z[0] = b->x;
+  z[1] = b->xp;
+  z[2] = b->y;
+  z[3] = b->yp;
+  z[4] = b->s;
+  z[5] = b->dp;
+}
+
+int grid_stride_blocks(int64_t n_total) {
+  const int64_t nb = nblocks(n_total);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nb, kMaxGridStride)));
+}
+
+struct Launch {
+  int pass0, npass, e0, e1;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ track
+extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
+                         const trk_opts *opts, void *workspace, size_t workspace_bytes_,
+                         void *stream) {
+  if (lat == nullptr || opts == nullptr) return fail(TRK_EINVAL, "lattice or opts is NULL");
+  if (passes < 0) return fail(TRK_EINVAL, "passes < 0");
+  if (opts->wake_mode != TRK_WAKE_FP64 && opts->wake_mode != TRK_WAKE_FP32_MFMA)
+    return fail(TRK_EINVAL, "unknown wake_mode");
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  if (opts->moments != nullptr)
+    if (int r = check_dev(opts->moments, "opts.moments")) return r;
+  const int nelem = static_cast<int>(lat->rec.size());
+  if (passes == 0 || nelem == 0 || beam->n_total == 0) return TRK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  double *z[6];
+  beam_ptrs(beam, z);
+  const bool mom = opts->moments != nullptr;
+
+  // pass-varying constants: reference momentum through the RF cavities
+  std::vector<double> vconst(static_cast<size_t>(passes) * std::max(lat->nvar, 1) * 2, 0.0);
+  {
+    double P = opts->p_ref_eV;
+    for (int p = 0; p < passes; ++p)
+      for (int e = 0; e < nelem; ++e) {
+        const trk_element &s = lat->src[e];
+        const int v = lat->vslot[e];
+        if (s.kind == TRK_RFCA) {
+          const double pn = P + s.volt * std::cos(s.phase);
+          vconst[2 * (static_cast<size_t>(p) * lat->nvar + v)] = P;
+          vconst[2 * (static_cast<size_t>(p) * lat->nvar + v) + 1] = pn;
+          P = pn;
+        } else if (s.kind == TRK_WAKE) {
+          const double kfac = ((s.charge / static_cast<double>(beam->n_total)) * s.wake_A) / P;
+          vconst[2 * (static_cast<size_t>(p) * lat->nvar + v)] = kfac;
+        }
+      }
+  }
+
+  // launch plan
+  std::vector<Launch> plan;
+  const int max_e = opts->max_elems_per_launch > 0 ? opts->max_elems_per_launch : nelem;
+  auto nvar_in = [&](int e0, int e1) {
+    int c = 0;
+    for (int e = e0; e < e1; ++e) c += lat->vslot[e] >= 0;
+    return c;
+  };
+  if (!lat->has_wake && max_e >= nelem) {
+    int ppl = opts->passes_per_launch > 0 ? opts->passes_per_launch : 16;
+    ppl = std::min(ppl, mom ? kMomPassesMax : kMaxPassesPerLaunch);
+    if (lat->nvar > 0) ppl = std::min(ppl, std::max(1, kMaxVar / lat->nvar));
+    if (lat->nvar > kMaxVar) return fail(TRK_ERANGE, "too many RF cavities in one lattice run");
+    for (int p = 0; p < passes; p += ppl) plan.push_back({p, std::min(ppl, passes - p), 0, nelem});
+  } else {
+    for (int p = 0; p < passes; ++p) {
+      int e0 = 0;
+      while (e0 < nelem) {
+        int e1 = e0 + 1;
+        // extend up to the next wake, the element limit and the constant slots
+        while (e1 < nelem && lat->src[e1].kind != TRK_WAKE && e1 - e0 < max_e &&
+               nvar_in(e0, e1 + 1) <= kMaxVar)
+          ++e1;
+        plan.push_back({p, 1, e0, e1});
+        e0 = e1;
+      }
+    }
+  }
+
+  if (mom) {
+    // shift for the fused one-pass moments: the mean at entry
+    const int g = static_cast<int>(std::min<int64_t>(nblocks(beam->n_total), 1024));
+    HIP_TRY(launch_mom_partial(z, beam->n_alive, beam->n_total, nullptr, w.mom_part, g, st),
+            "moments");
+    HIP_TRY(launch_mom_finalize(w.mom_part, g, 1, nullptr, w.mom_tmp, 28, w.mom_shift, st),
+            "moments");
+  }
+
+  const int nblk = static_cast<int>(nblocks(beam->n_total));
+  int prev_mm_n = 0;  // > 0: the previous launch left (min, max) partials
+  for (size_t li = 0; li < plan.size(); ++li) {
+    const Launch &L = plan[li];
+    const bool starts_wake = lat->src[L.e0].kind == TRK_WAKE;
+    if (starts_wake) {
+      const int nb = lat->src[L.e0].nbins;
+      if (prev_mm_n == 0) {
+        prev_mm_n = grid_stride_blocks(beam->n_total);
+        HIP_TRY(launch_minmax(beam->s, beam->n_alive, beam->n_total, w.mm_part, prev_mm_n, w.counts,
+                              TRK_MAX_BINS, st),
+                "minmax");
+      }
+      HIP_TRY(launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part, prev_mm_n, nb,
+                               w.counts, w.range, st),
+              "histogram");
+      HIP_TRY(launch_convolve(w.counts, nb, w.range, lat->src[L.e0].wake_tau0,
+                              lat->src[L.e0].wake_omega, opts->wake_mode, w.wake_v, w.wake_par, st),
+              "convolve");
+    }
+    // does the next launch start with a wake?
+    bool next_wake = false;
+    if (li + 1 < plan.size()) next_wake = lat->src[plan[li + 1].e0].kind == TRK_WAKE;
+    const bool lmom = mom && L.e1 == nelem;
+
+    RunArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int k = 0; k < 6; ++k) a.z[k] = z[k];
+    a.id = beam->id;
+    a.lost_at = beam->lost_at;
+    a.n_alive = beam->n_alive;
+    a.elems = lat->d_rec;
+    a.pool = lat->d_pool;
+    a.e0 = L.e0;
+    a.e1 = L.e1;
+    a.pass0 = opts->first_pass + L.pass0;
+    a.npass = L.npass;
+    a.seed_lo = static_cast<uint32_t>(opts->seed);
+    a.seed_hi = static_cast<uint32_t>(opts->seed >> 32);
+    uint32_t rd = 0, wr = 0;
+    bool any_aper = false;
+    int v0 = -1, nv = 0;
+    uint32_t feat = 0;
+    for (int e = L.e0; e < L.e1; ++e) {
+      switch (lat->rec[e].kind) {
+        case K_KQUAD:
+        case K_CSBEND: feat |= F_KD; break;
+        case K_RFCA: feat |= F_RF; break;
+        case K_WAKE: feat |= F_WAKE; break;
+        case K_RADKICK: feat |= F_RNG; break;
+        case K_MAP2_GEN: feat |= F_GEN; break;
+        default: break;
+      }
+      rd |= lat->rd[e];
+      wr |= lat->wr[e];
+      any_aper = any_aper || lat->aper[e];
+      if (lat->vslot[e] >= 0) {
+        if (v0 < 0) v0 = lat->vslot[e];
+        ++nv;
+      }
+    }
+    if (lmom) rd |= M_ALL;
+    if (next_wake) rd |= M_S;
+    a.feat = feat;
+    a.ldmask = rd | (wr & M_ALL);
+    a.stmask = wr & M_ALL;
+    a.v0 = v0 < 0 ? 0 : v0;
+    a.nv = nv;
+    for (int p = 0; p < L.npass; ++p)
+      for (int j = 0; j < nv; ++j) {
+        const size_t src = 2 * (static_cast<size_t>(L.pass0 + p) * lat->nvar + (a.v0 + j));
+        a.vc[p * nv + j][0] = vconst[src];
+        a.vc[p * nv + j][1] = vconst[src + 1];
+      }
+    a.wake_v = w.wake_v;
+    a.wake_par = w.wake_par;
+    a.mom = lmom ? 1 : 0;
+    a.mom_part = w.mom_part;
+    a.mom_shift = w.mom_shift;
+    const int grid = lmom ? std::max(nblk, 1) : grid_stride_blocks(beam->n_total);
+    if (next_wake) {
+      a.mm_part = w.mm_part;
+      a.zero_buf = w.counts;
+      a.zero_n = TRK_MAX_BINS;
+    }
+    HIP_TRY(profiled(0, st, [&] { return launch_run(a, grid, st); }), "run kernel");
+    prev_mm_n = next_wake ? grid : 0;
+    if (lmom) {
+      double *out = opts->moments + static_cast<size_t>(L.pass0) * 28;
+      HIP_TRY(launch_mom_finalize(w.mom_part, grid, L.npass, w.mom_shift, out, 28, nullptr, st),
+              "moments");
+    }
+    if (any_aper)
+      HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
+              "compact");
+  }
+  return TRK_OK;
+}
+
+// ------------------------------------------------------------------ collective calls
+extern "C" int trk_histogram(const trk_beam *beam, int32_t nbins, double *range_dev,
+                             uint32_t *counts_dev, void *workspace, size_t workspace_bytes_,
+                             void *stream) {
+  if (nbins < 2 || nbins > TRK_MAX_BINS) return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_BINS");
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_dev(counts_dev, "counts")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  const int g = grid_stride_blocks(beam->n_total);
+  HIP_TRY(launch_minmax(beam->s, beam->n_alive, beam->n_total, w.mm_part, g, counts_dev, nbins, st),
+          "minmax");
+  HIP_TRY(launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part, g, nbins, counts_dev,
+                           range_dev, st),
+          "histogram");
+  return TRK_OK;
+}
+
+extern "C" int trk_wake_convolve(const uint32_t *counts_dev, int32_t nbins, const double *range_dev,
+                                 double tau0, double omega, int32_t mode, double *v_dev,
+                                 void *stream) {
+  if (nbins < 2 || nbins > TRK_MAX_BINS) return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_BINS");
+  if (mode != TRK_WAKE_FP64 && mode != TRK_WAKE_FP32_MFMA) return fail(TRK_EINVAL, "unknown mode");
+  if (!(tau0 > 0.0)) return fail(TRK_EINVAL, "tau0 must be > 0");
+  if (int r = check_dev(counts_dev, "counts")) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_dev(v_dev, "v")) return r;
+  HIP_TRY(launch_convolve(counts_dev, nbins, range_dev, tau0, omega, mode, v_dev, nullptr,
+                          static_cast<hipStream_t>(stream)),
+          "convolve");
+  return TRK_OK;
+}
+
+extern "C" int trk_wake_kick(trk_beam *beam, const uint32_t *counts_dev, int32_t nbins,
+                             const double *range_dev, const trk_wake *wk, double p_ref_eV,
+                             int32_t mode, void *workspace, size_t workspace_bytes_, void *stream) {
+  if (wk == nullptr) return fail(TRK_EINVAL, "wake is NULL");
+  if (nbins < 2 || nbins > TRK_MAX_BINS) return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_BINS");
+  if (mode != TRK_WAKE_FP64 && mode != TRK_WAKE_FP32_MFMA) return fail(TRK_EINVAL, "unknown mode");
+  if (!(wk->tau0 > 0.0)) return fail(TRK_EINVAL, "tau0 must be > 0");
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(counts_dev, "counts")) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  if (beam->n_total == 0) return TRK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  HIP_TRY(launch_convolve(counts_dev, nbins, range_dev, wk->tau0, wk->omega, mode, w.wake_v,
+                          w.wake_par, st),
+          "convolve");
+  const double kfac = ((wk->charge / static_cast<double>(beam->n_total)) * wk->A) / p_ref_eV;
+  HIP_TRY(launch_wake_kick(beam->s, beam->dp, beam->n_alive, beam->n_total, w.wake_v, w.wake_par,
+                           nbins, kfac, st),
+          "wake kick");
+  return TRK_OK;
+}
+
+extern "C" int trk_moments(const trk_beam *beam, double *out_dev, void *workspace,
+                           size_t workspace_bytes_, void *stream) {
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(out_dev, "out")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  double *z[6];
+  beam_ptrs(beam, z);
+  const int g = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nblocks(beam->n_total), 1024)));
+  HIP_TRY(launch_mom_partial(z, beam->n_alive, beam->n_total, nullptr, w.mom_part, g, st), "moments");
+  HIP_TRY(launch_mom_finalize(w.mom_part, g, 1, nullptr, w.mom_tmp, 28, w.mom_shift, st), "moments");
+  HIP_TRY(launch_mom_partial(z, beam->n_alive, beam->n_total, w.mom_shift, w.mom_part, g, st),
+          "moments");
+  HIP_TRY(launch_mom_finalize(w.mom_part, g, 1, w.mom_shift, out_dev, 28, nullptr, st), "moments");
+  return TRK_OK;
+}
+
+extern "C" int trk_compact_lost(trk_beam *beam, void *workspace, size_t workspace_bytes_,
+                                void *stream) {
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  if (beam->n_total == 0) return TRK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  double *z[6];
+  beam_ptrs(beam, z);
+  HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
+          "compact");
+  return TRK_OK;
+}
+
+// ------------------------------------------------------------------ test hooks
+extern "C" int trk_elementary(int32_t fn, const double *x_dev, const double *y_dev, double *out_dev,
+                              int64_t n, void *stream) {
+  if (fn < 0 || fn > 5) return fail(TRK_EINVAL, "fn must be 0..5");
+  if (n < 0) return fail(TRK_EINVAL, "n < 0");
+  if (n == 0) return TRK_OK;
+  if (int r = check_dev(x_dev, "x")) return r;
+  if (fn == 5)
+    if (int r = check_dev(y_dev, "y")) return r;
+  if (int r = check_dev(out_dev, "out")) return r;
+  HIP_TRY(launch_elementary(fn, x_dev, y_dev, out_dev, n, static_cast<hipStream_t>(stream)),
+          "elementary");
+  return TRK_OK;
+}
+
+extern "C" int trk_philox4x32_10(const uint32_t *ctr_dev, const uint32_t *key_dev,
+                                 uint32_t *out_dev, int64_t n, void *stream) {
+  if (n < 0) return fail(TRK_EINVAL, "n < 0");
+  if (n == 0) return TRK_OK;
+  if (int r = check_dev(ctr_dev, "ctr")) return r;
+  if (int r = check_dev(key_dev, "key")) return r;
+  if (int r = check_dev(out_dev, "out")) return r;
+  HIP_TRY(launch_philox(ctr_dev, key_dev, out_dev, n, static_cast<hipStream_t>(stream)), "philox");
+  return TRK_OK;
+}
+
+extern "C" int trk_gauss(const uint32_t *id_dev, uint32_t step, uint32_t tag, uint64_t seed,
+                         double *out_dev, int64_t n, void *stream) {
+  if (n < 0) return fail(TRK_EINVAL, "n < 0");
+  if (n == 0) return TRK_OK;
+  if (int r = check_dev(id_dev, "id")) return r;
+  if (int r = check_dev(out_dev, "out")) return r;
+  HIP_TRY(launch_gauss(id_dev, step, tag, seed, out_dev, n, static_cast<hipStream_t>(stream)),
+          "gauss");
+  return TRK_OK;
+}
+
+// ------------------------------------------------------------------ misc
+extern "C" const char *trk_status_string(int status) {
+  switch (status) {
+    case TRK_OK: return "ok";
+    case TRK_EINVAL: return "invalid argument";
+    case TRK_EPTR: return "host pointer where a device pointer is required";
+    case TRK_EHIP: return "HIP runtime error";
+    case TRK_ENOMEM: return "out of device memory";
+    case TRK_ERANGE: return "size out of range";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char *trk_last_error(void) { return g_err.c_str(); }
+
+extern "C" int trk_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  if (on) {
+    for (int c = 0; c < 4; ++c) {
+      for (auto &p : g_prof.ev[c]) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+      }
+      g_prof.ev[c].clear();
+      g_prof.ms[c] = 0.0;
+      g_prof.launches[c] = 0;
+    }
+  }
+  return TRK_OK;
+}
+
+extern "C" int trk_profile_read(int32_t cls, double *total_ms, int64_t *launches) {
+  if (cls < 0 || cls > 3 || total_ms == nullptr || launches == nullptr)
+    return fail(TRK_EINVAL, "bad profile query");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto &p : g_prof.ev[cls]) {
+    HIP_TRY(hipEventSynchronize(p.second), "event sync");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.first, p.second), "event time");
+    g_prof.ms[cls] += ms;
+    g_prof.launches[cls] += 1;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  g_prof.ev[cls].clear();
+  *total_ms = g_prof.ms[cls];
+  *launches = g_prof.launches[cls];
+  return TRK_OK;
+}

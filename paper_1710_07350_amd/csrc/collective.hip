@@ -1,0 +1,341 @@
+// collective.hip -- the cross-particle steps: range of s, histogram, wake
+// convolution (binary64 sequential and FP32 matrix-core), wake kick and beam
+// moments.
+#include "elements.h"
+#include "reduce.h"
+
+namespace trk {
+
+constexpr double kCLight = 299792458.0;
+
+// ------------------------------------------------------------------ range
+__global__ __launch_bounds__(kBlock) void k_minmax(const double *__restrict__ s,
+                                                   const int64_t *__restrict__ n_alive,
+                                                   double *__restrict__ part, uint32_t *zero_buf,
+                                                   int zero_n) {
+  const int64_t n = *n_alive;
+  if (zero_buf != nullptr && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < zero_n; i += kBlock) zero_buf[i] = 0u;
+  double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const double v = s[i];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  block_minmax(mn, mx);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = mn;
+    part[2 * blockIdx.x + 1] = mx;
+  }
+}
+
+hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_total, double *mm_part,
+                         int grid, uint32_t *zero_buf, int zero_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(kBlock), 0, st, s, n_alive, mm_part, zero_buf,
+                     zero_n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ histogram
+// Per-wave sub-histograms in LDS cut the contention of lanes hitting the same
+// bin (the paper's sub-histogram scheme, Sec. 2.2); blocks then add their
+// non-zero bins to the global counts with integer atomics (exact, so the
+// result is order-free).  Every block reduces the (min, max) partials of the
+// preceding kernel itself, in the same order, so no extra launch is needed.
+__global__ __launch_bounds__(kBlock) void k_histogram(const double *__restrict__ s,
+                                                      const int64_t *__restrict__ n_alive,
+                                                      const double *__restrict__ mm_part, int mm_n,
+                                                      int nbins, int nsub,
+                                                      uint32_t *__restrict__ counts,
+                                                      double *__restrict__ range) {
+  extern __shared__ uint32_t sub[];  // [nsub][nbins], nsub divides kWaves
+  const int64_t n = *n_alive;
+  double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
+  for (int j = threadIdx.x; j < mm_n; j += kBlock) {
+    mn = fmin(mn, mm_part[2 * j]);
+    mx = fmax(mx, mm_part[2 * j + 1]);
+  }
+  block_minmax(mn, mx);
+  if (!(mn <= mx)) {  // nobody alive
+    mn = 0.0;
+    mx = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    range[0] = mn;
+    range[1] = mx;
+  }
+  const double width = mx - mn;
+  const double inv = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
+  for (int j = threadIdx.x; j < nsub * nbins; j += kBlock) sub[j] = 0u;
+  __syncthreads();
+  uint32_t *mine = sub + ((threadIdx.x >> 6) % nsub) * nbins;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const double f = (s[i] - mn) * inv;
+    if (f >= 0.0) {
+      int b = static_cast<int>(f);
+      if (b > nbins - 1) b = nbins - 1;
+      atomicAdd(mine + b, 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += kBlock) {
+    uint32_t c = 0;
+    for (int w = 0; w < nsub; ++w) c += sub[w * nbins + b];
+    if (c != 0u) atomicAdd(counts + b, c);
+  }
+}
+
+hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
+                            const double *mm_part, int mm_n, int nbins, uint32_t *counts,
+                            double *range, hipStream_t st) {
+  const int64_t want = (n_total + kBlock * 16 - 1) / (kBlock * 16);
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > 512 ? 512 : want));
+  // one sub-histogram per wave while they fit in 32 KB of LDS
+  int nsub = kWaves;
+  while (nsub > 1 && static_cast<size_t>(nsub) * nbins * sizeof(uint32_t) > 32768) nsub >>= 1;
+  const size_t lds = sizeof(uint32_t) * nsub * nbins;
+  hipLaunchKernelGGL(k_histogram, dim3(grid), dim3(kBlock), lds, st, s, n_alive, mm_part, mm_n,
+                     nbins, nsub, counts, range);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ convolution
+// Normalised resonator wake on the bin lags: W~[0] = 1/2 (a particle sees
+// half of its own wake), W~[m] = exp(-t/tau0) cos(omega t), t = m * delta / c.
+__device__ __forceinline__ double wake_table_entry(int m, double dt, double tau0, double omega) {
+  if (m == 0) return 0.5;
+  const double t = static_cast<double>(m) * dt;
+  return dm::own_exp(-(t / tau0)) * dm::own_cos(omega * t);
+}
+
+// Binary64: V[i] = sum_{j<=i} c_j W~[i-j], j ascending, one fma chain per
+// output -- the plain causal convolution, bit-exact with a sequential CPU loop.
+__global__ __launch_bounds__(1024) void k_conv_fp64(const uint32_t *__restrict__ counts, int nbins,
+                                                    const double *__restrict__ range, double tau0,
+                                                    double omega, double *__restrict__ v,
+                                                    double *__restrict__ wake_par) {
+  __shared__ double W[TRK_MAX_BINS];
+  __shared__ uint32_t C[TRK_MAX_BINS];
+  const double smin = range[0], smax = range[1];
+  const double width = smax - smin;
+  const double delta = width > 0.0 ? width / static_cast<double>(nbins) : 0.0;
+  const double dt = delta / kCLight;
+  for (int m = threadIdx.x; m < nbins; m += blockDim.x) {
+    W[m] = wake_table_entry(m, dt, tau0, omega);
+    C[m] = counts[m];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc = fma(static_cast<double>(C[j]), W[i - j], acc);
+    v[i] = acc;
+  }
+  if (threadIdx.x == 0 && wake_par != nullptr) {
+    wake_par[0] = smin;
+    wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
+  }
+}
+
+// FP32 on the matrix cores.  With V, c laid out as 16-row matrices
+// Vm[b][a] = V[16a+b], the causal convolution is a sum of products of
+// lower-Toeplitz 16x16 tiles T_d[b][b'] = W~[16d+b-b'] with column-shifted
+// count tiles S_d[b'][a] = c[16(a-d)+b']:  Vm = sum_d T_d S_d  -- a dense
+// contraction of depth nbins that v_mfma_f32_16x16x4_f32 executes.  Wave w
+// takes d = w, w+16, ...; the 16 wave partials are added in wave order
+// (deterministic).  W~ and c are rounded once to binary32 (c exact < 2^24).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(1024) void k_conv_mfma(const uint32_t *__restrict__ counts, int nbins,
+                                                    const double *__restrict__ range, double tau0,
+                                                    double omega, double *__restrict__ v,
+                                                    double *__restrict__ wake_par) {
+  __shared__ float Wf[TRK_MAX_BINS];
+  __shared__ float Cf[TRK_MAX_BINS];
+  __shared__ float Vs[TRK_MAX_BINS];
+  const double smin = range[0], smax = range[1];
+  const double width = smax - smin;
+  const double delta = width > 0.0 ? width / static_cast<double>(nbins) : 0.0;
+  const double dt = delta / kCLight;
+  for (int m = threadIdx.x; m < nbins; m += blockDim.x) {
+    Wf[m] = static_cast<float>(wake_table_entry(m, dt, tau0, omega));
+    Cf[m] = static_cast<float>(counts[m]);
+    Vs[m] = 0.0f;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nwave = blockDim.x >> 6;
+  const int a16 = (nbins + 15) >> 4;      // 16-wide columns of Vm
+  const int g16 = (a16 + 15) >> 4;        // 16-column output tiles
+  const int r = lane & 15, kq = lane >> 4;
+  f32x4 acc[TRK_MAX_BINS / 256];
+#pragma unroll
+  for (int g = 0; g < TRK_MAX_BINS / 256; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int d = wave; d < a16; d += nwave) {
+#pragma unroll
+    for (int g = 0; g < TRK_MAX_BINS / 256; ++g) {
+      if (g >= g16 || 16 * g + 15 < d) continue;  // wave-uniform: tile entirely acausal
+      const int col = 16 * g + r;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int k = 4 * kb + kq;
+        const int m = 16 * d + r - k;
+        const float av = (m >= 0 && m < nbins) ? Wf[m] : 0.0f;
+        const int jj = 16 * (col - d) + k;
+        const float bv = (col >= d && jj < nbins) ? Cf[jj] : 0.0f;
+        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[g], 0, 0, 0);
+      }
+    }
+  }
+  for (int w = 0; w < nwave; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int g = 0; g < TRK_MAX_BINS / 256; ++g) {
+        if (g >= g16) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 4 * kq + q;
+          const int idx = 16 * (16 * g + r) + row;
+          if (idx < nbins) Vs[idx] += acc[g][q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int m = threadIdx.x; m < nbins; m += blockDim.x) v[m] = static_cast<double>(Vs[m]);
+  if (threadIdx.x == 0 && wake_par != nullptr) {
+    wake_par[0] = smin;
+    wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
+  }
+}
+
+hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
+                           double omega, int mode, double *v, double *wake_par, hipStream_t st) {
+  if (mode == TRK_WAKE_FP32_MFMA)
+    hipLaunchKernelGGL(k_conv_mfma, dim3(1), dim3(1024), 0, st, counts, nbins, range, tau0, omega,
+                       v, wake_par);
+  else
+    hipLaunchKernelGGL(k_conv_fp64, dim3(1), dim3(1024), 0, st, counts, nbins, range, tau0, omega,
+                       v, wake_par);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ wake kick
+__global__ __launch_bounds__(kBlock) void k_wake_kick(const double *__restrict__ s,
+                                                      double *__restrict__ dp,
+                                                      const int64_t *__restrict__ n_alive,
+                                                      const double *__restrict__ v,
+                                                      const double *__restrict__ wake_par,
+                                                      int nbins, double kfac) {
+  const int64_t n = *n_alive;
+  const double smin = wake_par[0], inv = wake_par[1];
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const double vs = el::wake_interp(s[i], smin, inv, v, nbins);
+    dp[i] = fma(-kfac, vs, dp[i]);
+  }
+}
+
+hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64_t n_total,
+                            const double *v, const double *wake_par, int nbins, double kfac,
+                            hipStream_t st) {
+  const int64_t want = nblocks(n_total);
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxGridStride ? kMaxGridStride : want));
+  hipLaunchKernelGGL(k_wake_kick, dim3(grid), dim3(kBlock), 0, st, s, dp, n_alive, v, wake_par,
+                     nbins, kfac);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ moments
+// Shifted sums over survivors: row = (n, sum d_k, sum d_k d_l (k<=l)),
+// d = z - shift.  Each thread accumulates its particles in index order, then
+// the block sums in fixed order: deterministic for a given grid.
+struct Z6 {
+  const double *p[6];
+};
+
+__global__ __launch_bounds__(kBlock) void k_mom_partial(Z6 z, const int64_t *__restrict__ n_alive,
+                                                        const double *__restrict__ shift,
+                                                        double *__restrict__ part) {
+  const int64_t n = *n_alive;
+  double c[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c[k] = shift ? shift[k] : 0.0;
+  double acc[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) acc[k] = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double d[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d[k] = z.p[k][i] - c[k];
+    acc[0] += 1.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[1 + k] += d[k];
+    int o = 7;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = k; l < 6; ++l) acc[o++] += d[k] * d[l];
+  }
+  const double *tot = block_sum<28>(acc);
+  if (threadIdx.x < 28) part[static_cast<int64_t>(blockIdx.x) * 28 + threadIdx.x] = tot[threadIdx.x];
+}
+
+hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                              const double *shift, double *part, int grid, hipStream_t st) {
+  Z6 zz;
+  for (int k = 0; k < 6; ++k) zz.p[k] = z[k];
+  hipLaunchKernelGGL(k_mom_partial, dim3(grid), dim3(kBlock), 0, st, zz, n_alive, shift, part);
+  return hipGetLastError();
+}
+
+// One block per pass: sum the rows in fixed order, then
+// mean_k = shift_k + S_k/n, cov_kl = S_kl/n - (S_k/n)(S_l/n).
+__global__ __launch_bounds__(kBlock) void k_mom_finalize(const double *__restrict__ part, int nrows,
+                                                         const double *__restrict__ shift,
+                                                         double *__restrict__ out, int out_stride,
+                                                         double *__restrict__ mean_out) {
+  const double *pp = part + static_cast<int64_t>(blockIdx.x) * nrows * 28;
+  double acc[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) acc[k] = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 28; ++k) acc[k] += pp[static_cast<int64_t>(r) * 28 + k];
+  }
+  const double *tot = block_sum<28>(acc);
+  if (threadIdx.x == 0) {
+    double *o = out + static_cast<int64_t>(blockIdx.x) * out_stride;
+    const double n = tot[0];
+    double m[6];
+    for (int k = 0; k < 6; ++k) m[k] = tot[1 + k] / n;
+    o[0] = n;
+    for (int k = 0; k < 6; ++k) {
+      const double c = shift ? shift[k] : 0.0;
+      o[1 + k] = c + m[k];
+      if (mean_out) mean_out[k] = c + m[k];
+    }
+    int idx = 7;
+    for (int k = 0; k < 6; ++k)
+      for (int l = k; l < 6; ++l, ++idx) o[idx] = tot[idx] / n - m[k] * m[l];
+  }
+}
+
+hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const double *shift,
+                               double *out, int out_stride, double *mean_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mom_finalize, dim3(npass), dim3(kBlock), 0, st, part, nrows, shift, out,
+                     out_stride, mean_out);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace trk

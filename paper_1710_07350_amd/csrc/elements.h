@@ -1,0 +1,237 @@
+// elements.h -- per-particle element maps (device).
+//
+// z = (x, x', y, y', s, delta).  Each map fixes its operation order; fma
+// appears only where written (the library is built without contraction).
+// Physical content, by element (the element table of Sec. 3 of the paper):
+//   EDRIFT  exact drift (Sec. 2.1 listings): x += x'L, y += y'L and the path
+//           excess L(sqrt(1+u) - 1) = L u / (1 + sqrt(1+u)), u = x'^2 + y'^2.
+//   MAP2    z_i = C_i + sum_j R_ij z_j + sum_{j<=k} T_ijk z_j z_k from the
+//           input vector: non-zero terms only, order C, R by ascending j, T by
+//           ascending (j,k); the first term starts the sum (coefficient times
+//           coordinates), each later term is added with one fma; products
+//           z_j z_k rounded once.  A row whose only term is R_ii = 1 is exact.
+//   MULT    thin kick Delta px - i Delta py = -(KnL/n!)(x+iy)^n on canonical
+//           px = x'(1+delta)/sqrt(1+x'^2+y'^2), back to x' = px/pz.
+//   KQUAD   4th-order symplectic kick-drift (Yoshida): kicks
+//           Delta px = -l k1 x, Delta py = +l k1 y, canonical exact drifts.
+//   CSBEND  the sector-bend Hamiltonian -(1+hx)pz + hx + h^2x^2/2 split into
+//           a curved-frame drift (straight line, solved in polar form) and the
+//           kick Delta px = -l h (1 + hx).
+//   RFCA    zero-length cavity: delta <- (delta P + V (cos(phi+ks) - cos phi))/P',
+//           P' = P + V cos phi, the difference as -2 sin(phi+ks/2) sin(ks/2).
+#pragma once
+#include "devmath.h"
+#include "trk_internal.h"
+
+namespace trk {
+namespace el {
+
+__device__ __forceinline__ void edrift(double (&z)[6], double L) {
+  const double xp = z[1], yp = z[3];
+  const double u = fma(xp, xp, yp * yp);
+  z[0] = fma(xp, L, z[0]);
+  z[2] = fma(yp, L, z[2]);
+  z[4] = fma(L, u / (1.0 + sqrt(1.0 + u)), z[4]);
+}
+
+// thick-quad sparsity pattern: every listed coefficient is non-zero
+__device__ __forceinline__ void map_p1(double (&z)[6], const double *__restrict__ c) {
+  const double x = z[0], xp = z[1], y = z[2], yp = z[3], s = z[4], d = z[5];
+  const double xd = x * d, xpd = xp * d, yd = y * d, ypd = yp * d;
+  double a;
+  a = c[0] * x; a = fma(c[1], xp, a); a = fma(c[2], xd, a); a = fma(c[3], xpd, a);
+  z[0] = a;
+  a = c[4] * x; a = fma(c[5], xp, a); a = fma(c[6], xd, a); a = fma(c[7], xpd, a);
+  z[1] = a;
+  a = c[8] * y; a = fma(c[9], yp, a); a = fma(c[10], yd, a); a = fma(c[11], ypd, a);
+  z[2] = a;
+  a = c[12] * y; a = fma(c[13], yp, a); a = fma(c[14], yd, a); a = fma(c[15], ypd, a);
+  z[3] = a;
+  a = c[16] * s;
+  a = fma(c[17], x * x, a);
+  a = fma(c[18], x * xp, a);
+  a = fma(c[19], xp * xp, a);
+  a = fma(c[20], y * y, a);
+  a = fma(c[21], y * yp, a);
+  a = fma(c[22], yp * yp, a);
+  z[4] = a;
+  z[5] = c[23] * d;
+}
+
+// identity + R56 + T566 (a chicane)
+__device__ __forceinline__ void map_p2(double (&z)[6], const double *__restrict__ c) {
+  const double s = z[4], d = z[5];
+  z[0] = c[0] * z[0];
+  z[1] = c[1] * z[1];
+  z[2] = c[2] * z[2];
+  z[3] = c[3] * z[3];
+  double a = c[4] * s;
+  a = fma(c[5], d, a);
+  a = fma(c[7], d * d, a);
+  z[4] = a;
+  z[5] = c[6] * d;
+}
+
+// any second-order map: coefficient tests are wave-uniform branches
+__device__ __forceinline__ void map_gen(double (&z)[6], const double *__restrict__ c) {
+  double in[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) in[k] = z[k];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+    bool have = false;
+    const double ci = c[i];
+    if (ci != 0.0) {
+      a = ci;
+      have = true;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double r = c[6 + 6 * i + j];
+      if (r != 0.0) {
+        a = have ? fma(r, in[j], a) : r * in[j];
+        have = true;
+      }
+    }
+    int p = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int k = j; k < 6; ++k, ++p) {
+        const double t = c[42 + 21 * i + p];
+        if (t != 0.0) {
+          const double m = in[j] * in[k];
+          a = have ? fma(t, m, a) : t * m;
+          have = true;
+        }
+      }
+    z[i] = a;
+  }
+}
+
+struct Canon {
+  double px, py, opd, opd2;
+};
+
+__device__ __forceinline__ Canon canonical(const double (&z)[6]) {
+  Canon c;
+  c.opd = 1.0 + z[5];
+  c.opd2 = c.opd * c.opd;
+  const double xp = z[1], yp = z[3];
+  const double u = fma(xp, xp, yp * yp);
+  const double pz = c.opd / sqrt(1.0 + u);
+  c.px = xp * pz;
+  c.py = yp * pz;
+  return c;
+}
+
+__device__ __forceinline__ void slopes(double (&z)[6], const Canon &c) {
+  const double q = fma(c.px, c.px, c.py * c.py);
+  const double pz = sqrt(c.opd2 - q);
+  const double r = 1.0 / pz;
+  z[1] = c.px * r;
+  z[3] = c.py * r;
+}
+
+__device__ __forceinline__ void mult(double (&z)[6], double kn, int order) {
+  Canon c = canonical(z);
+  const double x = z[0], y = z[2];
+  double re = x, im = y;
+  for (int m = 2; m <= order; ++m) {
+    const double nre = (re * x) - (im * y);
+    const double nim = (re * y) + (im * x);
+    re = nre;
+    im = nim;
+  }
+  c.px = fma(-kn, re, c.px);
+  c.py = fma(kn, im, c.py);
+  slopes(z, c);
+}
+
+__device__ __forceinline__ void canon_drift(double (&z)[6], Canon &c, double dl) {
+  const double q = fma(c.px, c.px, c.py * c.py);
+  const double pz = sqrt(c.opd2 - q);
+  const double t = dl / pz;
+  z[0] = fma(c.px, t, z[0]);
+  z[2] = fma(c.py, t, z[2]);
+  z[4] = fma(q, t / (c.opd + pz), z[4]);
+}
+
+__device__ __forceinline__ void kquad(double (&z)[6], const double *__restrict__ k, int nsteps) {
+  Canon c = canonical(z);
+  for (int st = 0; st < nsteps; ++st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double kq = k[i];
+      c.px = fma(-kq, z[0], c.px);
+      c.py = fma(kq, z[2], c.py);
+      if (i < 3) canon_drift(z, c, k[4 + i]);
+    }
+  }
+  slopes(z, c);
+}
+
+__device__ __forceinline__ void csbend(double (&z)[6], const double *__restrict__ k, int nsteps) {
+  Canon c = canonical(z);
+  const double iopd = 1.0 / c.opd;
+  for (int st = 0; st < nsteps; ++st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c.px = c.px - fma(k[4 + i], z[0], k[i]);
+      if (i < 3) {
+        const double cph = k[8 + i], sph = k[11 + i], vers = k[14 + i], rs = k[17 + i];
+        const double arc = k[20 + i];
+        const double x = z[0];
+        const double q = fma(c.px, c.px, c.py * c.py);
+        const double pz = sqrt(c.opd2 - q);
+        const double pxn = fma(c.px, cph, pz * sph);
+        const double pzn = fma(pz, cph, -(c.px * sph));
+        const double tau = (fma(x, sph, rs) * c.opd) / pzn;
+        const double g = tau * iopd;
+        z[0] = fma(g, pxn, fma(x, cph, -vers));
+        z[2] = fma(g, c.py, z[2]);
+        z[4] = z[4] + (tau - arc);
+        c.px = pxn;
+      }
+    }
+  }
+  slopes(z, c);
+}
+
+__device__ __forceinline__ void rfca(double (&z)[6], double hk, double phase, double volt,
+                                     double pin, double pout) {
+  const double a = hk * z[4];
+  const double dc = (-2.0 * dm::own_sin(phase + a)) * dm::own_sin(a);
+  const double num = fma(z[5], pin, volt * dc);
+  z[5] = num / pout;
+}
+
+// V(s): linear between bin centres, constant beyond the first and last
+__device__ __forceinline__ double wake_interp(double s, double smin, double inv,
+                                              const double *__restrict__ v, int nbins) {
+  const double f = (s - smin) * inv - 0.5;
+  const double fl = floor(f);
+  int i0;
+  if (!(fl >= 0.0))
+    i0 = 0;
+  else if (fl > static_cast<double>(nbins - 2))
+    i0 = nbins - 2;
+  else
+    i0 = static_cast<int>(fl);
+  double w = f - static_cast<double>(i0);
+  if (!(w >= 0.0)) w = 0.0;
+  if (w > 1.0) w = 1.0;
+  const double v0 = v[i0];
+  return fma(w, v[i0 + 1] - v0, v0);
+}
+
+__device__ __forceinline__ bool aperture_lost(int aper, double a0, double a1, const double (&z)[6]) {
+  if (aper == TRK_APER_RECT) return !(fabs(z[0]) < a0 && fabs(z[2]) < a1);
+  const double xa = z[0] * a0, ya = z[2] * a1;
+  const double q = fma(xa, xa, ya * ya);
+  return !(q < 1.0);
+}
+
+}  // namespace el
+}  // namespace trk

@@ -1,0 +1,135 @@
+// trk_internal.h -- device records, kernel arguments and launch helpers
+// shared by the HIP translation units of libtrk.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/trk.h"
+
+namespace trk {
+
+constexpr int kBlock = 256;        // threads per block of the particle kernels
+constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
+constexpr int kMaxGridStride = 2048;
+constexpr int kMaxPassesPerLaunch = 64;
+
+// Device element kinds after host-side classification.  MAP2 maps are
+// evaluated through one of three code paths with identical arithmetic:
+// P1 = the thick-quad sparsity pattern, P2 = identity + R56 + T566, GEN = any.
+enum DevKind : int32_t {
+  K_EDRIFT = 1,
+  K_MAP2_P1 = 2,
+  K_MAP2_P2 = 3,
+  K_MAP2_GEN = 4,
+  K_MULT = 5,
+  K_KQUAD = 6,
+  K_CSBEND = 7,
+  K_RFCA = 8,
+  K_WAKE = 9,
+  K_RADKICK = 10,
+  K_MARKER = 11,
+};
+
+// Element families present in a run; the run kernel is instantiated per set
+// so that a run of light elements does not pay the registers of heavy ones.
+enum Feat : uint32_t { F_KD = 1, F_RF = 2, F_WAKE = 4, F_RNG = 8, F_GEN = 16, F_ALL = 31 };
+
+// 80-byte record read by every lane of a wave at the same address (scalar
+// loads); `off` indexes the lattice's constant pool.
+struct DevElem {
+  int32_t kind, aper, ip, off;  // ip: MULT order | KQUAD/CSBEND steps | WAKE bins
+  int32_t vslot, pad0, pad1, pad2;
+  double a0, a1;                // RECT: (X, Y); ELLIPSE: (1/a, 1/b)
+  double p0, p1, p2, p3;        // kind-specific scalars
+};
+static_assert(sizeof(DevElem) == 80, "DevElem layout");
+
+// Pool layouts (offsets from DevElem::off):
+//   MAP2_P1   24: x:(R11 R12 T116 T126) x':(R21 R22 T216 T226)
+//                 y:(R33 R34 T336 T346) y':(R43 R44 T436 T446)
+//                 s:(R55 T511 T512 T522 T533 T534 T544) delta:(R66)
+//   MAP2_P2    8: R11 R22 R33 R44 R55 R56 R66 T566
+//   MAP2_GEN 168: C[6] R[6][6] T[6][21]
+//   KQUAD      7: kq[4] dl[3]
+//   CSBEND    23: kA[4] kB[4] cph[3] sph[3] vers[3] rs[3] dl[3]
+// Scalars: EDRIFT p0 = L; MULT p0 = KnL/n!; RFCA p0 = k/2, p1 = phase,
+//   p2 = V; RADKICK p0 = sigma; WAKE ip = nbins.
+// Pass-varying constants vc[slot] = (a, b): RFCA (P_in, P_out), WAKE (kfac, 0).
+
+struct RunArgs {
+  double *z[6];
+  uint32_t *id;
+  int64_t *lost_at;
+  const int64_t *n_alive;
+  const DevElem *elems;
+  const double *pool;
+  int32_t e0, e1;       // element range of each pass
+  int32_t pass0, npass; // global first pass, passes in this launch
+  int32_t v0, nv;       // varying-constant slots of [e0, e1)
+  uint32_t seed_lo, seed_hi;
+  uint32_t ldmask, stmask;  // bit k: coordinate k loaded / stored; bit 6: id
+  uint32_t feat;            // element families present (selects the instantiation)
+  int32_t pad_;
+  const double *wake_v;     // V[nbins] when elements[e0] is a WAKE
+  const double *wake_par;   // (smin, 1/delta)
+  double *mm_part;          // [gridDim.x][2] (min s, max s) of survivors, or null
+  uint32_t *zero_buf;       // zeroed by block 0 when non-null
+  int32_t zero_n;
+  int32_t mom;              // per-pass moment partials
+  double *mom_part;         // [npass][gridDim.x][28]
+  const double *mom_shift;  // [6]
+  double vc[kMaxVar][2];
+};
+
+// ---------------------------------------------------------------- workspace
+struct Workspace {
+  double *mm_part;     // [kMaxGridStride][2]
+  uint32_t *counts;    // [TRK_MAX_BINS]
+  double *range;       // [2]
+  double *wake_par;    // [2]
+  double *wake_v;      // [TRK_MAX_BINS]
+  double *mom_shift;   // [6]
+  double *mom_tmp;     // [28]
+  double *mom_part;    // [kMaxPassesPerLaunch][nblk][28]
+  int64_t *cmp_blk;    // [nblk][10]
+  int64_t *cmp_hdr;    // [16]
+  uint64_t *key_a, *key_b;  // [n]
+  uint32_t *pos_a, *pos_b;  // [n]
+  double *tz[6];       // [n] scatter staging
+  uint32_t *tid;       // [n]
+  int64_t *tlost;      // [n]
+};
+size_t workspace_bytes(int64_t n_total);
+Workspace carve_workspace(void *base, int64_t n_total);
+
+inline int64_t nblocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
+
+// ---------------------------------------------------------------- launchers
+// (each returns hipSuccess or the launch error; all asynchronous)
+hipError_t launch_run(const RunArgs &a, int grid, hipStream_t st);
+hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_total, double *mm_part,
+                         int grid, uint32_t *zero_buf, int zero_n, hipStream_t st);
+hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
+                            const double *mm_part, int mm_n, int nbins, uint32_t *counts,
+                            double *range, hipStream_t st);
+hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
+                           double omega, int mode, double *v, double *wake_par, hipStream_t st);
+hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64_t n_total,
+                            const double *v, const double *wake_par, int nbins, double kfac,
+                            hipStream_t st);
+hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                              const double *shift, double *part, int grid, hipStream_t st);
+hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const double *shift,
+                               double *out, int out_stride, double *mean_out, hipStream_t st);
+hipError_t launch_compact(double *const z[6], uint32_t *id, int64_t *lost_at, int64_t *n_alive,
+                          int64_t n_total, const Workspace &w, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
+hipError_t launch_elementary(int fn, const double *x, const double *y, double *out, int64_t n,
+                             hipStream_t st);
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
+                         hipStream_t st);
+hipError_t launch_gauss(const uint32_t *id, uint32_t step, uint32_t tag, uint64_t seed,
+                        double *out, int64_t n, hipStream_t st);
+
+}  // namespace trk

@@ -1,0 +1,49 @@
+"""The C-ABI library loads on a host without a GPU and exports every function
+that include/trk.h declares (no compute calls here)."""
+import os
+import re
+import subprocess
+
+from paper_1710_07350_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "trk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(trk_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_set():
+    assert declared() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.lib()
+    nm = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(trk_\w+)", nm))
+    for name in declared():
+        assert name in exported, name
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_sizes():
+    lib = binding.lib()
+    assert lib.trk_status_string(0) == b"ok"
+    assert lib.trk_status_string(binding.TRK_EPTR).startswith(b"host pointer")
+    # workspace grows with the beam and is at least the staging copy (60 B/particle)
+    small = lib.trk_workspace_size(None, 1000)
+    big = lib.trk_workspace_size(None, 1_000_000)
+    assert big > small and big >= 60 * 1_000_000
+
+
+def test_invalid_lattice_rejected_without_gpu():
+    from paper_1710_07350_amd.inputs import Element
+    import pytest
+    with pytest.raises(binding.TrkError) as e:
+        binding.Lattice([Element("WAKE", nbins=1, wake_tau0=1e-11)])
+    assert e.value.status == binding.TRK_EINVAL
+    with pytest.raises(binding.TrkError):
+        binding.Lattice([Element("MULT", k=1.0, order=0)])

@@ -1,0 +1,295 @@
+"""Parity of the HIP path with the CPU oracle on identical seeded inputs.
+
+Binary64 tracking, loss records, survivor order, histogram counts and
+Philox streams are bit-exact; moments agree to 1e-12 of the beam scale; the
+FP32 matrix-core wake convolution stays inside its rounding-error bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_07350_amd import binding as B
+from paper_1710_07350_amd import inputs
+from paper_1710_07350_amd.inputs import Element
+
+from helpers import assert_bit_exact, moments_close, rel_err, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+WIDE = (2e-3, 2e-4, 2e-3, 2e-4, 1e-3, 1e-3)   # wide enough to lose particles
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+# ------------------------------------------------------------------ FODO
+def test_fodo_parity_with_moments(torch):
+    lat = inputs.fodo_lattice()
+    d = inputs.gaussian_beam(10_000, seed=0, sigmas=WIDE)
+    g = run_gpu(lat, d, 100, moments=True)
+    r = run_oracle(lat, d, 100, moments=True)
+    assert 0 < r["n_alive"] < 10_000
+    assert_bit_exact(g, r)
+    moments_close(g["moments"], r["moments"])
+
+
+@pytest.mark.parametrize("kw", [dict(passes_per_launch=1), dict(passes_per_launch=7),
+                                dict(max_elems_per_launch=5), dict(max_elems_per_launch=1)])
+def test_fodo_fusion_depth_does_not_change_results(torch, kw):
+    lat = inputs.fodo_lattice()
+    d = inputs.gaussian_beam(3000, seed=4, sigmas=WIDE)
+    r = run_oracle(lat, d, 12)
+    g = run_gpu(lat, d, 12, **kw)
+    assert_bit_exact(g, r)
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4099])
+def test_ragged_sizes(torch, n):
+    lat = inputs.fodo_lattice(ncells=3)
+    d = inputs.gaussian_beam(n, seed=n, sigmas=WIDE)
+    assert_bit_exact(run_gpu(lat, d, 9, moments=True), run_oracle(lat, d, 9, moments=True))
+
+
+def test_every_particle_lost(torch):
+    lat = inputs.fodo_lattice(ncells=2, aper=1e-4)
+    d = inputs.gaussian_beam(2000, seed=2, sigmas=WIDE)
+    g = run_gpu(lat, d, 4, moments=True)
+    r = run_oracle(lat, d, 4, moments=True)
+    assert r["n_alive"] == 0
+    assert_bit_exact(g, r)
+    assert np.isnan(g["moments"][-1, 1:]).all() and g["moments"][-1, 0] == 0
+
+
+def test_first_pass_offset_and_markers(torch):
+    lat = inputs.fodo_lattice(ncells=2) + [Element("MARKER", aperture="ELLIPSE", ax=4e-3, ay=3e-3)]
+    d = inputs.gaussian_beam(4000, seed=9, sigmas=WIDE)
+    g = run_gpu(lat, d, 3, first_pass=40)
+    r = run_oracle(lat, d, 3, first_pass=40)
+    assert_bit_exact(g, r)
+    lost = g["lost_at"][g["lost_at"] >= 0]
+    assert lost.size and ((lost >> 32) >= 40).all()
+
+
+# ------------------------------------------------------------------ ring
+def test_ring_subset_parity(torch):
+    lat = inputs.ring_lattice(seed=0)
+    d = inputs.gaussian_beam(2000, seed=3, sigmas=(3e-3, 3e-4, 2e-3, 2e-4, 1e-3, 1e-3))
+    g = run_gpu(lat, d, 30, seed=77, moments=True)
+    r = run_oracle(lat, d, 30, seed=77, moments=True)
+    assert 0 < r["n_alive"] < 2000
+    assert_bit_exact(g, r)
+    moments_close(g["moments"], r["moments"])
+
+
+def test_ring_multistep_elements(torch):
+    lat = inputs.ring_lattice(seed=5, ncells=4, nsteps=3)
+    d = inputs.gaussian_beam(1500, seed=6)
+    assert_bit_exact(run_gpu(lat, d, 5, seed=1), run_oracle(lat, d, 5, seed=1))
+
+
+def test_generic_map_and_octupole(torch):
+    rng = np.random.default_rng(12)
+    c = np.zeros(168)
+    c[:6] = rng.normal(0, 1e-5, 6)
+    c[6:42] = (np.eye(6) + rng.normal(0, 0.05, (6, 6))).ravel()
+    c[42:] = rng.normal(0, 0.3, 126) * (rng.random(126) < 0.5)
+    lat = [Element("MAP2", coef=c, aperture="RECT", ax=4e-3, ay=4e-3),
+           Element("MULT", k=300.0, order=3), Element("QUAD", L=0.3, k=0.0),
+           Element("EDRIFT", L=0.7, aperture="RECT", ax=4e-3, ay=4e-3)]
+    d = inputs.gaussian_beam(3000, seed=8, sigmas=WIDE)
+    assert_bit_exact(run_gpu(lat, d, 6), run_oracle(lat, d, 6))
+
+
+# ------------------------------------------------------------------ bunch compressor
+def bc_bound_on_delta(d, lat, n0):
+    """|delta_fp32 - delta_fp64| bound after the 8 wake steps: each V value
+    errs by at most (nbins + 2) 2^-24 sum_j c_j |W[i-j]| (FP32 products, sums
+    and table rounding), interpolation is a convex combination, and the RF
+    kicks only scale earlier errors by P/P' < 1."""
+    nb = lat[1].nbins
+    rg, cnt = oracle.histogram(d["z"][4], d["lost_at"], nb)
+    w = oracle.wake_table(rg[0], rg[1], nb, lat[1].wake_tau0, lat[1].wake_omega)
+    scale = np.convolve(cnt.astype(float), np.abs(w))[:nb]
+    bound_v = (nb + 2) * 2.0 ** -24 * scale.max()
+    P = inputs.BC_P0_EV
+    tot = 0.0
+    for e in lat:
+        if e.kind == "RFCA":
+            P = P + e.volt * math.cos(e.phase)
+        if e.kind == "WAKE":
+            tot += oracle.wake_kfac(e.charge, n0, e.wake_A, P) * bound_v
+    return tot
+
+
+@pytest.mark.parametrize("n", [100_000, 4_000_000])
+def test_bunch_compressor_fp64_bit_exact(torch, n):
+    lat = inputs.bc_lattice()
+    d = inputs.gaussian_beam(n, seed=0, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+
+
+@pytest.mark.parametrize("n", [100_000, 4_000_000])
+def test_bunch_compressor_fp32_mfma_within_bound(torch, n):
+    lat = inputs.bc_lattice()
+    d = inputs.gaussian_beam(n, seed=0, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert g["n_alive"] == r["n_alive"] == n
+    assert np.array_equal(g["id"], r["id"])
+    for k in (0, 1, 2, 3):
+        assert np.array_equal(g["z"][k], r["z"][k])
+    bd = bc_bound_on_delta(d, lat, n)
+    err_d = np.abs(g["z"][5] - r["z"][5]).max()
+    assert err_d <= bd, (err_d, bd)
+    dmax = np.abs(r["z"][5]).max() + bd
+    err_s = np.abs(g["z"][4] - r["z"][4]).max()
+    assert err_s <= (0.05 + 2 * 0.075 * dmax) * bd * 1.0001 + 1e-18, (err_s, bd)
+    print(f"FP32 wake: max |d delta| = {err_d:.3e} (bound {bd:.3e}), max |d s| = {err_s:.3e}")
+
+
+# ------------------------------------------------------------------ collective calls
+def test_histogram_bit_exact(torch):
+    for n, nb in [(1, 8), (1000, 1024), (123457, 1024), (300000, 4096), (5000, 2)]:
+        d = inputs.gaussian_beam(n, seed=n)
+        beam = B.Beam.from_inputs(d)
+        ws = B.Workspace(beam.n)
+        rg, cnt = B.histogram(beam, nb, ws)
+        rr, rc = oracle.histogram(d["z"][4], d["lost_at"], nb)
+        assert np.array_equal(rg.cpu().numpy(), rr)
+        assert np.array_equal(cnt.cpu().numpy().view(np.uint32), rc)
+
+
+def test_histogram_nobody_alive(torch):
+    d = inputs.gaussian_beam(500, seed=1)
+    beam = B.Beam(d["z"], d["id"], d["lost_at"], n_alive=0)
+    ws = B.Workspace(beam.n)
+    rg, cnt = B.histogram(beam, 64, ws)
+    assert rg.cpu().numpy().tolist() == [0.0, 0.0] and int(cnt.sum()) == 0
+
+
+@pytest.mark.parametrize("nb", [2, 17, 1024, 4096])
+def test_convolution(torch, nb):
+    rng = np.random.default_rng(nb)
+    cnt = rng.integers(0, 20000, nb).astype(np.uint32)
+    rg = np.array([-2e-3, 3e-3])
+    tau0, om = 10e-12, 2 * math.pi * 50e9
+    w = oracle.wake_table(rg[0], rg[1], nb, tau0, om)
+    ref = oracle.convolve(cnt, w)
+    ct = torch.tensor(cnt.view(np.int32), device="cuda")
+    rt = torch.tensor(rg, device="cuda")
+    v64 = B.wake_convolve(ct, nb, rt, tau0, om, B.WAKE_FP64).cpu().numpy()
+    assert np.array_equal(v64, ref)
+    v32 = B.wake_convolve(ct, nb, rt, tau0, om, B.WAKE_FP32_MFMA).cpu().numpy()
+    scale = np.convolve(cnt.astype(float), np.abs(w))[:nb]
+    bound = (nb + 2) * 2.0 ** -24 * scale
+    assert np.all(np.abs(v32 - ref) <= bound + 1e-300)
+    print(f"nb={nb}: FP32 max rel err {np.max(np.abs(v32 - ref) / np.maximum(scale, 1e-300)):.2e}")
+
+
+def test_wake_kick_call(torch):
+    d = inputs.gaussian_beam(50_000, seed=5)
+    nb, tau0, om, A, Q, P = 256, 10e-12, 2 * math.pi * 50e9, 1e14, 1e-9, 1e8
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    rg, cnt = B.histogram(beam, nb, ws)
+    B.wake_kick(beam, cnt, nb, rg, A, tau0, om, Q, P, B.WAKE_FP64, ws)
+    got = beam.host()
+    ref = oracle.Beam.from_inputs(d)
+    rr, rc = oracle.histogram(ref.z[4], ref.lost_at, nb)
+    v = oracle.convolve(rc, oracle.wake_table(rr[0], rr[1], nb, tau0, om))
+    oracle.wake_kick(ref, rr, v, oracle.wake_kfac(Q, ref.n0, A, P))
+    assert np.array_equal(got["z"], ref.z)
+
+
+def test_moments_call(torch):
+    for n in (1, 2, 1000, 300_001):
+        d = inputs.gaussian_beam(n, seed=n)
+        d["z"] += np.array([[1e-3], [0], [-2e-3], [0], [0.3], [1e-3]])
+        beam = B.Beam.from_inputs(d)
+        ws = B.Workspace(beam.n)
+        g = B.moments(beam, ws).cpu().numpy()
+        r = oracle.moments(oracle.Beam.from_inputs(d))
+        if n == 1:
+            assert g[0] == 1 and np.array_equal(g[1:7], r[1:7]) and not g[7:].any()
+        else:
+            moments_close(g, r, rtol=1e-13)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.003, 0.05, 0.5, 1.0])
+def test_compaction_order(torch, frac):
+    rng = np.random.default_rng(int(frac * 1000) + 1)
+    n = 200_003
+    d = inputs.gaussian_beam(n, seed=11)
+    d["id"] = rng.permutation(n).astype(np.uint32)
+    sel = rng.random(n) < frac
+    la = np.full(n, -1, np.int64)
+    la[sel] = (rng.integers(5, 9, sel.sum()) << 32) | rng.integers(0, 401, sel.sum())
+    d["lost_at"] = la
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    B.compact_lost(beam, ws)
+    g = beam.host()
+    ref = oracle.Beam.from_inputs(d)
+    nal = oracle.compact(ref)
+    assert g["n_alive"] == nal
+    assert np.array_equal(g["id"], ref.id)
+    assert np.array_equal(g["lost_at"], ref.lost_at)
+    assert np.array_equal(g["z"], ref.z)
+
+
+def test_compaction_leaves_old_lost_region(torch):
+    """Particles beyond n_alive (lost earlier) are not touched."""
+    n = 10_000
+    d = inputs.gaussian_beam(n, seed=3)
+    la = np.full(n, -1, np.int64)
+    la[8000:] = 7 << 32
+    la[[10, 500, 7999]] = (9 << 32) | 3
+    d["lost_at"] = la
+    beam = B.Beam(d["z"], d["id"], la, n_alive=8000)
+    ws = B.Workspace(beam.n)
+    B.compact_lost(beam, ws)
+    g = beam.host()
+    assert g["n_alive"] == 7997
+    assert np.array_equal(g["id"][8000:], d["id"][8000:])
+    assert g["id"][7997:8000].tolist() == [10, 500, 7999]
+
+
+def test_host_pointer_rejected(torch):
+    import ctypes as C
+    d = inputs.gaussian_beam(100, seed=0)
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    host = np.zeros(100)
+    st = beam.struct()
+    st.x = host.ctypes.data
+    rc = B.lib().trk_compact_lost(C.byref(st), ws.ptr, ws.nbytes, None)
+    assert rc == B.TRK_EPTR
+    rc = B.lib().trk_compact_lost(C.byref(beam.struct()), ws.ptr, 16, None)
+    assert rc == B.TRK_ERANGE
+
+
+# ------------------------------------------------------------------ full-size, sampled
+def test_ring_full_size_sampled(torch):
+    """1e6 particles of the storage-ring workload, as tracked by the bench,
+    for 10 turns; 600 sampled particles re-tracked alone by the oracle
+    (particles are independent and the random kicks are keyed by id)."""
+    lat = inputs.ring_lattice(seed=0)
+    d = inputs.gaussian_beam(1_000_000, seed=0)
+    g = run_gpu(lat, d, 10, seed=2024)
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(1_000_000, 600, replace=False))
+    sub = {"z": d["z"][:, pick].copy(), "id": d["id"][pick].copy(), "lost_at": d["lost_at"][pick].copy()}
+    r = run_oracle(lat, sub, 10, seed=2024)
+    where = {int(i): j for j, i in enumerate(g["id"])}
+    rows = np.array([where[int(i)] for i in r["id"]])
+    assert np.array_equal(g["lost_at"][rows], r["lost_at"])
+    assert np.array_equal(g["z"][:, rows], r["z"])
+    assert (g["lost_at"][: g["n_alive"]] < 0).all()
