@@ -195,7 +195,9 @@ double orc_gauss(uint32_t id, uint32_t step, uint32_t tag, uint64_t seed) {
  * kick-drift-kick form: kicks c = (w1/2, (w0+w1)/2, (w0+w1)/2, w1/2),
  * drifts d = (w1, w0, w1), w1 = 1/(2 - 2^(1/3)), w0 = -2^(1/3)/(2 - 2^(1/3)). */
 void orc_yoshida(double c[4], double d[3]) {
-  double cr = cbrt(2.0);
+  /* 2^(1/3) correctly rounded (not libm's cbrt, which may differ by an ulp
+   * between a compile-time fold and a run-time call) */
+  double cr = 0x1.428a2f98d728bp+0;
   double w1 = 1.0 / (2.0 - cr);
   double w0 = -cr / (2.0 - cr);
   c[0] = 0.5 * w1;

@@ -99,7 +99,7 @@ hipError_t profiled(int cls, hipStream_t st, F &&launch) {
 // ------------------------------------------------------------------ constants
 // Fourth-order symmetric composition (Yoshida 1990): kicks c, drifts d.
 void yoshida(double c[4], double d[3]) {
-  const double cr = std::cbrt(2.0);
+  const double cr = 0x1.428a2f98d728bp+0;  // 2^(1/3), correctly rounded binary64
   const double w1 = 1.0 / (2.0 - cr);
   const double w0 = -cr / (2.0 - cr);
   c[0] = 0.5 * w1;

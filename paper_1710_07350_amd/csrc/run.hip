@@ -44,7 +44,9 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t stride = kMom ? 0 : static_cast<int64_t>(gridDim.x) * kBlock;
 
-  for (int64_t i = first; kMom ? (i == first) : (i < n); i += stride) {
+  // moments variant: exactly one particle per thread (every thread must reach
+  // the per-pass block reductions); otherwise a grid-stride loop
+  for (int64_t it = 0, i = first; kMom ? (it < 1) : (i < n); ++it, i += stride) {
     const bool act = i < n;
     double z[6];
 #pragma unroll

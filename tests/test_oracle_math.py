@@ -112,3 +112,6 @@ def test_yoshida_coefficients(orc):
     assert math.isclose(d.sum(), 1.0, rel_tol=0, abs_tol=4e-16)
     w1, w0 = d[0], d[1]
     assert math.isclose(2 * w1 ** 3 + w0 ** 3, 0.0, abs_tol=1e-14)
+    # w1 = 1/(2 - 2^(1/3)) from the correctly rounded cube root of 2
+    cr = float(mp.cbrt(2))
+    assert w1 == 1.0 / (2.0 - cr) and w0 == -cr / (2.0 - cr)
