@@ -123,7 +123,12 @@ typedef struct trk_opts {
                                    TRK_WAKE (0 = 16) */
   int32_t max_elems_per_launch; /* fusion depth in elements (0 = no limit) */
   int32_t wake_mode;            /* enum trk_wake_mode */
-  int32_t reserved0, reserved1;
+  int32_t run_ppt;              /* launch shape of the fused runs (0 = automatic):
+                                   particles per thread, 1, 2, 4 or 8 */
+  int32_t run_blocks;           /* grid cap of grid-stride runs (0 = automatic) */
+  int32_t run_longit;           /* runs touching only s and delta: 0 automatic
+                                   (two-coordinate kernel), -1 generic kernel */
+  int32_t reserved;
   double p_ref_eV;              /* reference momentum at the entry of the first
                                    pass [eV/c]; raised by V cos(phase) per RFCA */
   double *moments;              /* NULL or device [passes][28]: per pass, after its
@@ -183,6 +188,46 @@ int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t w
  * (scan, single-workgroup stable radix sort of the lost subset by a dense
  * rank of (pass, element), scatter), so the host never waits. */
 int trk_compact_lost(trk_beam *beam, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many variants of one lattice structure (same element kinds in the same
+ * order; strengths, apertures and seeds may differ), each with its own beam
+ * of uneven size, tracked in one persistent launch: work is split into
+ * (variant, chunk) tickets that a grid of a few blocks per compute unit pulls
+ * from an atomic counter.  Every particle's result equals that of its
+ * variant tracked alone with trk_track (same element arithmetic, random
+ * kicks keyed by (id, pass) with the variant's seed).  Particles stay in
+ * place (no reordering); lost ones get their lost_at record.  RF cavities
+ * and wakes are not supported in batches.
+ *
+ * trk_batch_create: lats[nvar] lattices; seg_off[nvar+1] host offsets of the
+ * variants' segments in the concatenated beam (seg_off[0] = 0); seeds[nvar].
+ * Copies everything to a library-owned handle. */
+typedef struct trk_batch trk_batch;
+int trk_batch_create(const trk_lattice *const *lats, int32_t nvar, const int64_t *seg_off,
+                     const uint64_t *seeds, trk_batch **out);
+void trk_batch_destroy(trk_batch *b);
+
+/* Launch schedule (the autotuner's search space): ppt particles per thread
+ * (1, 2 or 4), blocks_per_cu persistent blocks per compute unit,
+ * passes_per_launch passes per persistent launch (0 = all), use_graph: 1 to
+ * capture the launch sequence in a hipGraph (captured on a stream the handle
+ * owns, cached on the handle, replayed on the caller's stream while the
+ * arguments repeat; a handle must not be used from two threads at once). */
+typedef struct trk_batch_tuning {
+  int32_t ppt, blocks_per_cu, passes_per_launch, use_graph;
+} trk_batch_tuning;
+
+/* workspace for moments of up to passes_per_launch passes per launch
+ * (64 at most) */
+size_t trk_batch_workspace_size(const trk_batch *b, int32_t passes_per_launch);
+
+/* beam: the concatenated beam (n_total = seg_off[nvar]; n_alive unused);
+ * moments_dev: NULL or [nvar][passes][28] (as trk_opts.moments, unshifted
+ * one-pass sums). */
+int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes, int32_t first_pass,
+                      const trk_batch_tuning *tune, double *moments_dev, void *workspace,
+                      size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------ test hooks
  * Bit-exactness probes of the device arithmetic used by the kernels.

@@ -454,13 +454,19 @@ static void csbend(double *z, const kd_const *k) {
 }
 
 /* Zero-length RF cavity (RFCA): energy gain V cos(phase + k s) with the
- * reference momentum raised by V cos(phase); the cosine difference is written
- * -2 sin(phase + ks/2) sin(ks/2). */
-static void rfca(double *z, double hk, double phase, double volt, double pin, double pn) {
+ * reference momentum raised to P' = P + V cos(phase):
+ *   delta' = (delta P + V (cos(phase + ks) - cos(phase))) / P'.
+ * The cosine difference is -2 sin(a) sin(phase + a), a = ks/2, with
+ * sin(phase + a) = sin(phase) cos(a) + cos(phase) sin(a) (no cancellation;
+ * sin/cos of the phase are element constants), and the division by P' is a
+ * multiplication by the element constant 1/P'. */
+static void rfca(double *z, double hk, double sph, double cph, double volt, double pin,
+                 double inv_pn) {
   double a = hk * z[4];
-  double dc = (-2.0 * orc_sin(phase + a)) * orc_sin(a);
+  double sa = orc_sin(a), ca = orc_cos(a);
+  double dc = (-2.0 * fma(sph, ca, cph * sa)) * sa;
   double num = fma(z[5], pin, volt * dc);
-  z[5] = num / pn;
+  z[5] = num * inv_pn;
 }
 
 static int aperture_lost(const orc_elem *e, const double *z) {
@@ -684,9 +690,12 @@ int64_t orc_track(orc_beam *b, const orc_elem *lat, int32_t nelem, int32_t passe
         free(w);
         free(v);
       }
-      double pin = P, pn = P, hk = 0.0;
+      double pin = P, pn = P, hk = 0.0, sph = 0.0, cph = 0.0, inv_pn = 0.0;
       if (el->kind == ORC_RFCA) {
-        pn = P + el->volt * cos(el->phase);
+        sph = sin(el->phase);
+        cph = cos(el->phase);
+        pn = P + el->volt * cph;
+        inv_pn = 1.0 / pn;
         hk = 0.5 * ((TWO_PI * el->freq) / C_LIGHT);
       }
       double kn = 0.0;
@@ -704,7 +713,7 @@ int64_t orc_track(orc_beam *b, const orc_elem *lat, int32_t nelem, int32_t passe
           case ORC_MULT: mult(z, kn, el->order); break;
           case ORC_KQUAD: kquad(z, &kd[e]); break;
           case ORC_CSBEND: csbend(z, &kd[e]); break;
-          case ORC_RFCA: rfca(z, hk, el->phase, el->volt, pin, pn); break;
+          case ORC_RFCA: rfca(z, hk, sph, cph, el->volt, pin, inv_pn); break;
           case ORC_RADKICK:
             z[5] = fma(el->sigma, orc_gauss(b->id[i], (uint32_t)gp, ORC_TAG_RAD, seed), z[5]);
             break;

@@ -26,7 +26,9 @@ MAX_BINS = 4096
 EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
            "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_moments",
            "trk_compact_lost", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
-           "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read")
+           "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
+           "trk_batch_create", "trk_batch_destroy", "trk_batch_workspace_size",
+           "trk_track_batched")
 
 
 class TrkError(RuntimeError):
@@ -54,8 +56,14 @@ class BeamStruct(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first_pass", C.c_int32),
                 ("passes_per_launch", C.c_int32), ("max_elems_per_launch", C.c_int32),
-                ("wake_mode", C.c_int32), ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+                ("wake_mode", C.c_int32), ("run_ppt", C.c_int32), ("run_blocks", C.c_int32),
+                ("run_longit", C.c_int32), ("reserved", C.c_int32),
                 ("p_ref_eV", C.c_double), ("moments", C.c_void_p)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("ppt", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("passes_per_launch", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class Wake(C.Structure):
@@ -96,6 +104,14 @@ def lib():
         L.trk_last_error.restype = C.c_char_p
         L.trk_profile_enable.argtypes = [i32]
         L.trk_profile_read.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.trk_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(u64),
+                                       C.POINTER(vp)]
+        L.trk_batch_destroy.argtypes = [vp]
+        L.trk_batch_destroy.restype = None
+        L.trk_batch_workspace_size.argtypes = [vp, i32]
+        L.trk_batch_workspace_size.restype = sz
+        L.trk_track_batched.argtypes = [vp, C.POINTER(BeamStruct), i32, i32,
+                                        C.POINTER(BatchTuning), vp, vp, sz, vp]
         _LIB = L
     return _LIB
 
@@ -202,8 +218,12 @@ class Workspace:
 # ------------------------------------------------------------------ calls
 def track(beam: Beam, lattice: Lattice, passes: int, ws: Workspace, seed: int = 0,
           first_pass: int = 0, p_ref: float = 1e9, moments=None, wake_mode: int = WAKE_FP64,
-          passes_per_launch: int = 0, max_elems_per_launch: int = 0, stream=None) -> None:
+          passes_per_launch: int = 0, max_elems_per_launch: int = 0, run_ppt: int = 0,
+          run_blocks: int = 0, run_longit: int = 0, stream=None) -> None:
     o = Opts()
+    o.run_ppt = run_ppt
+    o.run_blocks = run_blocks
+    o.run_longit = run_longit
     o.seed = seed
     o.first_pass = first_pass
     o.passes_per_launch = passes_per_launch
@@ -286,3 +306,43 @@ def profile_read(cls: int = 0):
     n = C.c_int64()
     _check(lib().trk_profile_read(cls, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """Variants of one lattice structure over a concatenated beam."""
+
+    def __init__(self, lattices, seg_off, seeds):
+        self.lattices = list(lattices)          # keep the handles alive
+        nvar = len(self.lattices)
+        hs = (C.c_void_p * nvar)(*[L.handle.value for L in self.lattices])
+        off = np.ascontiguousarray(seg_off, dtype=np.int64)
+        sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+        assert off.shape == (nvar + 1,) and sd.shape == (nvar,)
+        h = C.c_void_p()
+        _check(lib().trk_batch_create(hs, nvar, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      sd.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(h)))
+        self.handle = h
+        self.nvar = nvar
+        self.seg_off = off
+
+    def workspace(self, passes_per_launch: int = 64, device="cuda"):
+        import torch
+        n = int(lib().trk_batch_workspace_size(self.handle, passes_per_launch))
+        buf = torch.empty(n, dtype=torch.uint8, device=device)
+        return buf
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.trk_batch_destroy(h)
+            self.handle = None
+
+
+def track_batched(batch: Batch, beam: Beam, passes: int, ws, first_pass: int = 0, ppt: int = 1,
+                  blocks_per_cu: int = 2, passes_per_launch: int = 0, use_graph: bool = True,
+                  moments=None, stream=None) -> None:
+    t = BatchTuning(ppt, blocks_per_cu, passes_per_launch, 1 if use_graph else 0)
+    _check(lib().trk_track_batched(batch.handle, C.byref(beam.struct()), passes, first_pass,
+                                   C.byref(t), moments.data_ptr() if moments is not None else None,
+                                   ws.data_ptr(), ws.numel(), _stream_handle(stream)))

@@ -337,8 +337,9 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
         constexpr double kTwoPi = 0x1.921fb54442d18p+2;
         d.kind = K_RFCA;
         d.p0 = 0.5 * ((kTwoPi * s.freq) / 299792458.0);
-        d.p1 = s.phase;
-        d.p2 = s.volt;
+        d.p1 = std::sin(s.phase);
+        d.p2 = std::cos(s.phase);
+        d.p3 = s.volt;
         d.vslot = L->nvar++;
         rd = M_S | M_DP;
         wr = M_DP;
@@ -439,8 +440,8 @@ Workspace carve(void *base, int64_t n_total, size_t *bytes) {
   const size_t nb = static_cast<size_t>(std::max<int64_t>(nblocks(n_total), 1));
   Carver c{static_cast<char *>(base)};
   Workspace w;
-  w.mm_part = c.take<double>(2 * std::max<size_t>(nb, kMaxGridStride));
-  w.counts = c.take<uint32_t>(TRK_MAX_BINS);
+  w.mm_part = c.take<double>(2 * std::max<size_t>(nb, kMaxRunGrid));
+  w.counts = c.take<uint32_t>(TRK_MAX_BINS + 64);
   w.range = c.take<double>(2);
   w.wake_par = c.take<double>(2);
   w.wake_v = c.take<double>(TRK_MAX_BINS);
@@ -538,7 +539,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         if (s.kind == TRK_RFCA) {
           const double pn = P + s.volt * std::cos(s.phase);
           vconst[2 * (static_cast<size_t>(p) * lat->nvar + v)] = P;
-          vconst[2 * (static_cast<size_t>(p) * lat->nvar + v) + 1] = pn;
+          vconst[2 * (static_cast<size_t>(p) * lat->nvar + v) + 1] = 1.0 / pn;
           P = pn;
         } else if (s.kind == TRK_WAKE) {
           const double kfac = ((s.charge / static_cast<double>(beam->n_total)) * s.wake_A) / P;
@@ -585,7 +586,6 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
             "moments");
   }
 
-  const int nblk = static_cast<int>(nblocks(beam->n_total));
   int prev_mm_n = 0;  // > 0: the previous launch left (min, max) partials
   for (size_t li = 0; li < plan.size(); ++li) {
     const Launch &L = plan[li];
@@ -602,7 +602,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
                                w.counts, w.range, st),
               "histogram");
       HIP_TRY(launch_convolve(w.counts, nb, w.range, lat->src[L.e0].wake_tau0,
-                              lat->src[L.e0].wake_omega, opts->wake_mode, w.wake_v, w.wake_par, st),
+                              lat->src[L.e0].wake_omega, opts->wake_mode, w.wake_v, w.wake_par,
+                              st),
               "convolve");
     }
     // does the next launch start with a wake?
@@ -649,6 +650,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
     if (lmom) rd |= M_ALL;
     if (next_wake) rd |= M_S;
     a.feat = feat;
+    a.n_total = beam->n_total;
     a.ldmask = rd | (wr & M_ALL);
     a.stmask = wr & M_ALL;
     a.v0 = v0 < 0 ? 0 : v0;
@@ -664,7 +666,9 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
     a.mom = lmom ? 1 : 0;
     a.mom_part = w.mom_part;
     a.mom_shift = w.mom_shift;
-    const int grid = lmom ? std::max(nblk, 1) : grid_stride_blocks(beam->n_total);
+    a.longit = opts->run_longit >= 0 && !lmom && !any_aper &&
+               ((a.ldmask | a.stmask) & ~(M_S | M_DP)) == 0 && (feat & ~(F_RF | F_WAKE)) == 0;
+    const int grid = run_shape(a, beam->n_total, opts->run_ppt, opts->run_blocks);
     if (next_wake) {
       a.mm_part = w.mm_part;
       a.zero_buf = w.counts;
@@ -772,6 +776,238 @@ extern "C" int trk_compact_lost(trk_beam *beam, void *workspace, size_t workspac
   beam_ptrs(beam, z);
   HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
           "compact");
+  return TRK_OK;
+}
+
+// ------------------------------------------------------------------ batches
+struct trk_batch {
+  int nvar = 0, nelem = 0;
+  uint32_t feat = 0, ldmask = 0, stmask = 0;
+  std::vector<int64_t> seg_off;
+  std::vector<int64_t> chunk_off[3];  // ppt 1, 2, 4
+  DevElem *d_rec = nullptr;
+  double *d_pool = nullptr;
+  int64_t *d_seg_off = nullptr;
+  int64_t *d_chunk_off[3] = {nullptr, nullptr, nullptr};
+  uint64_t *d_seeds = nullptr;
+  int ncu = 0;
+  // cached graph of the last launch sequence, captured on a private stream
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<uint64_t> key;
+};
+
+namespace {
+int ppt_slot(int ppt) { return ppt >= 4 ? 2 : (ppt == 2 ? 1 : 0); }
+int ppt_of_slot(int k) { return k == 2 ? 4 : (k == 1 ? 2 : 1); }
+constexpr int kBatchMomPasses = 64;
+}  // namespace
+
+extern "C" int trk_batch_create(const trk_lattice *const *lats, int32_t nvar, const int64_t *seg_off,
+                                const uint64_t *seeds, trk_batch **out) {
+  if (out == nullptr) return fail(TRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nvar < 1 || lats == nullptr || seg_off == nullptr || seeds == nullptr)
+    return fail(TRK_EINVAL, "need nvar >= 1 lattices, offsets and seeds");
+  const int nelem = static_cast<int>(lats[0] ? lats[0]->rec.size() : 0);
+  if (nelem == 0) return fail(TRK_EINVAL, "empty lattice");
+  if (seg_off[0] != 0) return fail(TRK_EINVAL, "seg_off[0] must be 0");
+  std::vector<DevElem> rec;
+  std::vector<double> pool;
+  trk_batch *B = new (std::nothrow) trk_batch();
+  if (B == nullptr) return fail(TRK_ENOMEM, "host allocation failed");
+  B->nvar = nvar;
+  B->nelem = nelem;
+  for (int v = 0; v < nvar; ++v) {
+    const trk_lattice *L = lats[v];
+    if (L == nullptr || static_cast<int>(L->rec.size()) != nelem) {
+      delete B;
+      return fail(TRK_EINVAL, "batch lattices must have equal length");
+    }
+    if (seg_off[v + 1] < seg_off[v]) {
+      delete B;
+      return fail(TRK_EINVAL, "seg_off must be non-decreasing");
+    }
+    const int32_t shift = static_cast<int32_t>(pool.size());
+    for (int e = 0; e < nelem; ++e) {
+      if (L->src[e].kind != lats[0]->src[e].kind) {
+        delete B;
+        return fail(TRK_EINVAL, "batch lattices must have the same element kinds");
+      }
+      if (L->src[e].kind == TRK_RFCA || L->src[e].kind == TRK_WAKE) {
+        delete B;
+        return fail(TRK_EINVAL, "RF cavities and wakes are not supported in batches");
+      }
+      DevElem d = L->rec[e];
+      d.off += shift;
+      rec.push_back(d);
+      switch (d.kind) {
+        case K_KQUAD:
+        case K_CSBEND: B->feat |= F_KD; break;
+        case K_RADKICK: B->feat |= F_RNG; break;
+        case K_MAP2_GEN: B->feat |= F_GEN; break;
+        default: break;
+      }
+      B->ldmask |= L->rd[e] | L->wr[e];
+      B->stmask |= L->wr[e];
+    }
+    pool.insert(pool.end(), L->pool.begin(), L->pool.end());
+  }
+  B->ldmask &= 127u;
+  B->stmask &= 63u;
+  B->seg_off.assign(seg_off, seg_off + nvar + 1);
+  for (int k = 0; k < 3; ++k) {
+    const int64_t ch = static_cast<int64_t>(kBlock) * ppt_of_slot(k);
+    B->chunk_off[k].assign(nvar + 1, 0);
+    for (int v = 0; v < nvar; ++v)
+      B->chunk_off[k][v + 1] = B->chunk_off[k][v] + (seg_off[v + 1] - seg_off[v] + ch - 1) / ch;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&B->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipMalloc(&B->d_rec, rec.size() * sizeof(DevElem));
+  if (e == hipSuccess) e = hipMalloc(&B->d_pool, std::max<size_t>(1, pool.size()) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&B->d_seg_off, (nvar + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&B->d_seeds, nvar * sizeof(uint64_t));
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMalloc(&B->d_chunk_off[k], (nvar + 1) * sizeof(int64_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(B->d_rec, rec.data(), rec.size() * sizeof(DevElem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !pool.empty())
+    e = hipMemcpy(B->d_pool, pool.data(), pool.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(B->d_seg_off, seg_off, (nvar + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(B->d_seeds, seeds, nvar * sizeof(uint64_t), hipMemcpyHostToDevice);
+  for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    e = hipMemcpy(B->d_chunk_off[k], B->chunk_off[k].data(), (nvar + 1) * sizeof(int64_t),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    trk_batch_destroy(B);
+    return fail(e == hipErrorOutOfMemory ? TRK_ENOMEM : TRK_EHIP,
+                std::string("batch upload: ") + hipGetErrorString(e));
+  }
+  *out = B;
+  return TRK_OK;
+}
+
+extern "C" void trk_batch_destroy(trk_batch *b) {
+  if (b == nullptr) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  (void)hipFree(b->d_rec);
+  (void)hipFree(b->d_pool);
+  (void)hipFree(b->d_seg_off);
+  (void)hipFree(b->d_seeds);
+  for (int k = 0; k < 3; ++k) (void)hipFree(b->d_chunk_off[k]);
+  delete b;
+}
+
+extern "C" size_t trk_batch_workspace_size(const trk_batch *b, int32_t passes_per_launch) {
+  if (b == nullptr) return 0;
+  const int64_t ppl = std::max(1, std::min<int>(passes_per_launch <= 0 ? kBatchMomPasses : passes_per_launch,
+                                                kBatchMomPasses));
+  return 256 + static_cast<size_t>(b->chunk_off[0][b->nvar]) * ppl * 28 * sizeof(double) + 256;
+}
+
+namespace {
+// enqueue the launches of one batched call on st
+hipError_t batch_sequence(trk_batch *b, const trk_beam *beam, int passes, int first_pass,
+                          const trk_batch_tuning &tu, double *moments, uint32_t *ticket,
+                          double *mom_part, int ppl, hipStream_t st) {
+  const int k = ppt_slot(tu.ppt);
+  const int grid = std::max(1, tu.blocks_per_cu) * std::max(1, b->ncu);
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  double *z[6];
+  beam_ptrs(beam, z);
+  for (int q = 0; q < 6; ++q) a.z[q] = z[q];
+  a.id = beam->id;
+  a.lost_at = beam->lost_at;
+  a.seg_off = b->d_seg_off;
+  a.chunk_off = b->d_chunk_off[k];
+  a.seeds = b->d_seeds;
+  a.elems = b->d_rec;
+  a.pool = b->d_pool;
+  a.nelem = b->nelem;
+  a.nvar = b->nvar;
+  a.ldmask = b->ldmask | (moments ? M_ALL : 0u);
+  a.stmask = b->stmask;
+  a.ticket = ticket;
+  a.total = b->chunk_off[k][b->nvar];
+  a.mom_part = moments ? mom_part : nullptr;
+  for (int p0 = 0; p0 < passes; p0 += ppl) {
+    const int np = std::min(ppl, passes - p0);
+    a.pass0 = first_pass + p0;
+    a.npass = np;
+    hipError_t e = launch_zero_u32(ticket, 1, st);
+    if (e != hipSuccess) return e;
+    e = launch_batch(a, b->feat, ppt_of_slot(k), grid, st);
+    if (e != hipSuccess) return e;
+    if (moments) {
+      e = launch_batch_mom_finalize(mom_part, b->d_chunk_off[k], b->nvar, np, moments, p0, passes,
+                                    st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes,
+                                 int32_t first_pass, const trk_batch_tuning *tune,
+                                 double *moments_dev, void *workspace, size_t workspace_bytes_,
+                                 void *stream) {
+  if (b == nullptr || tune == nullptr) return fail(TRK_EINVAL, "batch or tuning is NULL");
+  if (passes < 0) return fail(TRK_EINVAL, "passes < 0");
+  if (int r = check_beam(beam)) return r;
+  if (beam->n_total != b->seg_off[b->nvar])
+    return fail(TRK_EINVAL, "beam.n_total must equal seg_off[nvar]");
+  int ppl = tune->passes_per_launch > 0 ? tune->passes_per_launch : passes;
+  if (moments_dev != nullptr) {
+    if (int r = check_dev(moments_dev, "moments")) return r;
+    ppl = std::min(ppl, kBatchMomPasses);
+  }
+  ppl = std::max(ppl, 1);
+  const size_t need = trk_batch_workspace_size(b, ppl);
+  if (workspace_bytes_ < need) return fail(TRK_ERANGE, "batch workspace too small");
+  if (int r = check_dev(workspace, "workspace")) return r;
+  if (passes == 0 || beam->n_total == 0) return TRK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t *ticket = static_cast<uint32_t *>(workspace);
+  double *mom_part = reinterpret_cast<double *>(static_cast<char *>(workspace) + 256);
+  if (!tune->use_graph) {
+    HIP_TRY(batch_sequence(b, beam, passes, first_pass, *tune, moments_dev, ticket, mom_part, ppl, st),
+            "batch");
+    return TRK_OK;
+  }
+  std::vector<uint64_t> key = {reinterpret_cast<uint64_t>(beam->x), reinterpret_cast<uint64_t>(beam->id),
+                               reinterpret_cast<uint64_t>(beam->lost_at), static_cast<uint64_t>(passes),
+                               static_cast<uint64_t>(static_cast<uint32_t>(first_pass)),
+                               static_cast<uint64_t>(tune->ppt), static_cast<uint64_t>(tune->blocks_per_cu),
+                               static_cast<uint64_t>(ppl), reinterpret_cast<uint64_t>(moments_dev),
+                               reinterpret_cast<uint64_t>(workspace)};
+  for (int q = 1; q < 6; ++q) key.push_back(reinterpret_cast<uint64_t>((&beam->x)[q]));
+  if (b->exec == nullptr || key != b->key) {
+    if (b->exec) {
+      HIP_TRY(hipGraphExecDestroy(b->exec), "graph destroy");
+      b->exec = nullptr;
+    }
+    if (b->cap == nullptr) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "stream");
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = batch_sequence(b, beam, passes, first_pass, *tune, moments_dev, ticket, mom_part,
+                                  ppl, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess) return hip_fail(e, "batch capture");
+    if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    b->key = key;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, st), "graph launch");
   return TRK_OK;
 }
 

@@ -1,0 +1,87 @@
+// apply.h -- one element applied to one particle, shared by the fused run
+// kernel and the batched persistent kernel.
+#pragma once
+#include "elements.h"
+
+namespace trk {
+
+// Rarely executed handlers stay out of line so that their registers do not
+// count against the hot element loop.
+static __device__ __noinline__ void radkick_call(double &dp, double sigma, uint32_t pid, uint32_t gp,
+                                          uint32_t klo, uint32_t khi) {
+  dp = fma(sigma, dm::gauss(pid, gp, 2u, klo, khi), dp);
+}
+static __device__ __noinline__ void map_gen_call(double (&z)[6], const double *__restrict__ c) {
+  el::map_gen(z, c);
+}
+
+// Lattice records and constants are read-only and read at wave-uniform
+// addresses: through the constant address space they are fetched with scalar
+// loads into SGPRs.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TRK_CONST __attribute__((address_space(4)))
+#else
+#define TRK_CONST
+#endif
+typedef const DevElem TRK_CONST *ConstElems;
+typedef const double TRK_CONST *ConstPool;
+__device__ __forceinline__ const double *cx_pool_generic(ConstPool pool, int off) {
+  return (const double *)(pool + off);
+}
+
+// What an element needs besides its record: pass-varying constants, the
+// wake table and the random-number key.
+struct ElemCtx {
+  const double (*vc)[2];
+  int nv, v0;
+  const double *wake_v;
+  const double *wake_par;
+  uint32_t seed_lo, seed_hi;
+};
+
+// One element applied to one particle (wave-uniform record E).
+template <uint32_t kFeat>
+__device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const ElemCtx &cx, int p,
+                                      uint32_t gp, int e, double (&z)[6], bool &alive,
+                                      int64_t &rec, uint32_t pid) {
+  if (!alive) return;
+  ConstPool c = pool + E.off;
+  switch (E.kind) {
+    case K_EDRIFT: el::edrift(z, E.p0); break;
+    case K_MAP2_P1: el::map_p1(z, c); break;
+    case K_MAP2_P2: el::map_p2(z, c); break;
+    case K_MULT: el::mult(z, E.p0, E.ip); break;
+    case K_MAP2_GEN:
+      if constexpr ((kFeat & F_GEN) != 0) map_gen_call(z, cx_pool_generic(pool, E.off));
+      break;
+    case K_KQUAD:
+      if constexpr ((kFeat & F_KD) != 0) el::kquad(z, c, E.ip);
+      break;
+    case K_CSBEND:
+      if constexpr ((kFeat & F_KD) != 0) el::csbend(z, c, E.ip);
+      break;
+    case K_RFCA:
+      if constexpr ((kFeat & F_RF) != 0) {
+        const int v = p * cx.nv + (E.vslot - cx.v0);
+        el::rfca(z, E.p0, E.p1, E.p2, E.p3, cx.vc[v][0], cx.vc[v][1]);
+      }
+      break;
+    case K_WAKE:
+      if constexpr ((kFeat & F_WAKE) != 0) {
+        const int v = p * cx.nv + (E.vslot - cx.v0);
+        const double vs = el::wake_interp(z[4], cx.wake_par[0], cx.wake_par[1], cx.wake_v, E.ip);
+        z[5] = fma(-cx.vc[v][0], vs, z[5]);
+      }
+      break;
+    case K_RADKICK:
+      if constexpr ((kFeat & F_RNG) != 0) radkick_call(z[5], E.p0, pid, gp, cx.seed_lo, cx.seed_hi);
+      break;
+    default: break;
+  }
+  if (E.aper != TRK_APER_NONE && el::aperture_lost(E.aper, E.a0, E.a1, z)) {
+    alive = false;
+    rec = static_cast<int64_t>((static_cast<uint64_t>(gp) << 32) | static_cast<uint32_t>(e));
+  }
+}
+
+}  // namespace trk

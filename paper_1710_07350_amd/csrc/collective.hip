@@ -38,25 +38,46 @@ hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_tota
 }
 
 // ------------------------------------------------------------------ histogram
-// Per-wave sub-histograms in LDS cut the contention of lanes hitting the same
-// bin (the paper's sub-histogram scheme, Sec. 2.2); blocks then add their
-// non-zero bins to the global counts with integer atomics (exact, so the
-// result is order-free).  Every block reduces the (min, max) partials of the
-// preceding kernel itself, in the same order, so no extra launch is needed.
-__global__ __launch_bounds__(kBlock) void k_histogram(const double *__restrict__ s,
-                                                      const int64_t *__restrict__ n_alive,
-                                                      const double *__restrict__ mm_part, int mm_n,
-                                                      int nbins, int nsub,
-                                                      uint32_t *__restrict__ counts,
-                                                      double *__restrict__ range) {
-  extern __shared__ uint32_t sub[];  // [nsub][nbins], nsub divides kWaves
+// Sub-histograms in LDS cut the contention of lanes hitting the same bin (the
+// paper's sub-histogram scheme, Sec. 2.2): one per group of waves, as many as
+// fit in 32 KB.  Blocks then add their non-zero bins to the global counts
+// with integer atomics (exact, so the result is order-free).  Every block
+// reduces the (min, max) partials of the preceding kernel itself, in the same
+// order, so no extra launch is needed.
+constexpr int kHistThreads = 1024;
+
+__global__ __launch_bounds__(kHistThreads) void k_histogram(const double *__restrict__ s,
+                                                            const int64_t *__restrict__ n_alive,
+                                                            const double *__restrict__ mm_part,
+                                                            int mm_n, int nbins, int nsub,
+                                                            uint32_t *__restrict__ counts,
+                                                            double *__restrict__ range) {
+  extern __shared__ uint32_t sub[];  // [nsub][nbins]
+  __shared__ double pm[kHistThreads / 64][2];
   const int64_t n = *n_alive;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
-  for (int j = threadIdx.x; j < mm_n; j += kBlock) {
+  for (int j = threadIdx.x; j < mm_n; j += kHistThreads) {
     mn = fmin(mn, mm_part[2 * j]);
     mx = fmax(mx, mm_part[2 * j + 1]);
   }
-  block_minmax(mn, mx);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, m, 64));
+    mx = fmax(mx, __shfl_xor(mx, m, 64));
+  }
+  if (lane == 0) {
+    pm[wave][0] = mn;
+    pm[wave][1] = mx;
+  }
+  for (int j = threadIdx.x; j < nsub * nbins; j += kHistThreads) sub[j] = 0u;
+  __syncthreads();
+  mn = pm[0][0];
+  mx = pm[0][1];
+  for (int w = 1; w < kHistThreads / 64; ++w) {
+    mn = fmin(mn, pm[w][0]);
+    mx = fmax(mx, pm[w][1]);
+  }
   if (!(mn <= mx)) {  // nobody alive
     mn = 0.0;
     mx = 0.0;
@@ -67,20 +88,23 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const double *__restrict__
   }
   const double width = mx - mn;
   const double inv = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
-  for (int j = threadIdx.x; j < nsub * nbins; j += kBlock) sub[j] = 0u;
-  __syncthreads();
-  uint32_t *mine = sub + ((threadIdx.x >> 6) % nsub) * nbins;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const double f = (s[i] - mn) * inv;
-    if (f >= 0.0) {
-      int b = static_cast<int>(f);
-      if (b > nbins - 1) b = nbins - 1;
-      atomicAdd(mine + b, 1u);
+  uint32_t *mine = sub + (wave % nsub) * nbins;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kHistThreads;
+  // four loads in flight per thread
+  constexpr int kU = 4;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kHistThreads + threadIdx.x; i < n;
+       i += kU * stride) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = i + u * stride < n ? s[i + u * stride] : -1.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const double f = (v[u] - mn) * inv;
+      if (i + u * stride < n && f >= 0.0) atomicAdd(mine + min(static_cast<int>(f), nbins - 1), 1u);
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < nbins; b += kBlock) {
+  for (int b = threadIdx.x; b < nbins; b += kHistThreads) {
     uint32_t c = 0;
     for (int w = 0; w < nsub; ++w) c += sub[w * nbins + b];
     if (c != 0u) atomicAdd(counts + b, c);
@@ -90,14 +114,13 @@ __global__ __launch_bounds__(kBlock) void k_histogram(const double *__restrict__
 hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
                             const double *mm_part, int mm_n, int nbins, uint32_t *counts,
                             double *range, hipStream_t st) {
-  const int64_t want = (n_total + kBlock * 16 - 1) / (kBlock * 16);
-  const int grid = static_cast<int>(want < 1 ? 1 : (want > 512 ? 512 : want));
-  // one sub-histogram per wave while they fit in 32 KB of LDS
-  int nsub = kWaves;
+  const int64_t want = (n_total + kHistThreads * 32 - 1) / (kHistThreads * 32);
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > 256 ? 256 : want));
+  int nsub = kHistThreads / 64;
   while (nsub > 1 && static_cast<size_t>(nsub) * nbins * sizeof(uint32_t) > 32768) nsub >>= 1;
   const size_t lds = sizeof(uint32_t) * nsub * nbins;
-  hipLaunchKernelGGL(k_histogram, dim3(grid), dim3(kBlock), lds, st, s, n_alive, mm_part, mm_n,
-                     nbins, nsub, counts, range);
+  hipLaunchKernelGGL(k_histogram, dim3(grid), dim3(kHistThreads), lds, st, s, n_alive, mm_part,
+                     mm_n, nbins, nsub, counts, range);
   return hipGetLastError();
 }
 
@@ -110,114 +133,109 @@ __device__ __forceinline__ double wake_table_entry(int m, double dt, double tau0
   return dm::own_exp(-(t / tau0)) * dm::own_cos(omega * t);
 }
 
+constexpr int kTile = 256;  // outputs per convolution workgroup
+
+__device__ __forceinline__ void write_wake_par(double smin, double width, int nbins,
+                                               double *wake_par) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && wake_par != nullptr) {
+    wake_par[0] = smin;
+    wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
+  }
+}
+
 // Binary64: V[i] = sum_{j<=i} c_j W~[i-j], j ascending, one fma chain per
-// output -- the plain causal convolution, bit-exact with a sequential CPU loop.
-__global__ __launch_bounds__(1024) void k_conv_fp64(const uint32_t *__restrict__ counts, int nbins,
-                                                    const double *__restrict__ range, double tau0,
-                                                    double omega, double *__restrict__ v,
-                                                    double *__restrict__ wake_par) {
+// output -- the plain causal convolution, bit-exact with a sequential CPU
+// loop.  Workgroup g owns outputs [256 g, 256 g + 256).
+__global__ __launch_bounds__(kTile) void k_conv_fp64(const uint32_t *__restrict__ counts, int nbins,
+                                                     const double *__restrict__ range, double tau0,
+                                                     double omega, double *__restrict__ v,
+                                                     double *__restrict__ wake_par) {
   __shared__ double W[TRK_MAX_BINS];
   __shared__ uint32_t C[TRK_MAX_BINS];
   const double smin = range[0], smax = range[1];
   const double width = smax - smin;
   const double delta = width > 0.0 ? width / static_cast<double>(nbins) : 0.0;
   const double dt = delta / kCLight;
-  for (int m = threadIdx.x; m < nbins; m += blockDim.x) {
+  const int hi = min(nbins, kTile * static_cast<int>(blockIdx.x + 1));
+  for (int m = threadIdx.x; m < hi; m += kTile) {
     W[m] = wake_table_entry(m, dt, tau0, omega);
     C[m] = counts[m];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+  const int i = kTile * blockIdx.x + threadIdx.x;
+  if (i < nbins) {
     double acc = 0.0;
     for (int j = 0; j <= i; ++j) acc = fma(static_cast<double>(C[j]), W[i - j], acc);
     v[i] = acc;
   }
-  if (threadIdx.x == 0 && wake_par != nullptr) {
-    wake_par[0] = smin;
-    wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
-  }
+  write_wake_par(smin, width, nbins, wake_par);
 }
 
 // FP32 on the matrix cores.  With V, c laid out as 16-row matrices
 // Vm[b][a] = V[16a+b], the causal convolution is a sum of products of
 // lower-Toeplitz 16x16 tiles T_d[b][b'] = W~[16d+b-b'] with column-shifted
-// count tiles S_d[b'][a] = c[16(a-d)+b']:  Vm = sum_d T_d S_d  -- a dense
-// contraction of depth nbins that v_mfma_f32_16x16x4_f32 executes.  Wave w
-// takes d = w, w+16, ...; the 16 wave partials are added in wave order
-// (deterministic).  W~ and c are rounded once to binary32 (c exact < 2^24).
+// count tiles S_d[b'][a] = c[16(a-d)+b']:  Vm = sum_d T_d S_d, a dense
+// contraction that v_mfma_f32_16x16x4_f32 executes.  Workgroup g owns the
+// 16 columns (256 outputs) of tile g and needs d < 16g + 16; its 16 waves
+// split d and their partial tiles are added in wave order (deterministic).
+// W~ and c are rounded once to binary32 (c is exact below 2^24).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kConvWaves = 16;
 
-__global__ __launch_bounds__(1024) void k_conv_mfma(const uint32_t *__restrict__ counts, int nbins,
-                                                    const double *__restrict__ range, double tau0,
-                                                    double omega, double *__restrict__ v,
-                                                    double *__restrict__ wake_par) {
+__global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
+    const uint32_t *__restrict__ counts, int nbins, const double *__restrict__ range, double tau0,
+    double omega, double *__restrict__ v, double *__restrict__ wake_par) {
   __shared__ float Wf[TRK_MAX_BINS];
   __shared__ float Cf[TRK_MAX_BINS];
-  __shared__ float Vs[TRK_MAX_BINS];
+  __shared__ float part[kConvWaves][kTile];
   const double smin = range[0], smax = range[1];
   const double width = smax - smin;
   const double delta = width > 0.0 ? width / static_cast<double>(nbins) : 0.0;
   const double dt = delta / kCLight;
-  for (int m = threadIdx.x; m < nbins; m += blockDim.x) {
-    Wf[m] = static_cast<float>(wake_table_entry(m, dt, tau0, omega));
-    Cf[m] = static_cast<float>(counts[m]);
-    Vs[m] = 0.0f;
+  const int g = blockIdx.x;
+  const int hi = kTile * (g + 1);  // entries this tile can touch
+  for (int m = threadIdx.x; m < hi; m += blockDim.x) {
+    Wf[m] = m < nbins ? static_cast<float>(wake_table_entry(m, dt, tau0, omega)) : 0.0f;
+    Cf[m] = m < nbins ? static_cast<float>(counts[m]) : 0.0f;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nwave = blockDim.x >> 6;
-  const int a16 = (nbins + 15) >> 4;      // 16-wide columns of Vm
-  const int g16 = (a16 + 15) >> 4;        // 16-column output tiles
   const int r = lane & 15, kq = lane >> 4;
-  f32x4 acc[TRK_MAX_BINS / 256];
+  const int col = 16 * g + r;  // Vm column of this lane's B operand
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int d = wave; d < 16 * g + 16; d += kConvWaves) {
 #pragma unroll
-  for (int g = 0; g < TRK_MAX_BINS / 256; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int d = wave; d < a16; d += nwave) {
-#pragma unroll
-    for (int g = 0; g < TRK_MAX_BINS / 256; ++g) {
-      if (g >= g16 || 16 * g + 15 < d) continue;  // wave-uniform: tile entirely acausal
-      const int col = 16 * g + r;
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        const int k = 4 * kb + kq;
-        const int m = 16 * d + r - k;
-        const float av = (m >= 0 && m < nbins) ? Wf[m] : 0.0f;
-        const int jj = 16 * (col - d) + k;
-        const float bv = (col >= d && jj < nbins) ? Cf[jj] : 0.0f;
-        acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[g], 0, 0, 0);
-      }
+    for (int kb = 0; kb < 4; ++kb) {
+      const int k = 4 * kb + kq;
+      const int m = 16 * d + r - k;
+      const float av = m >= 0 ? Wf[m] : 0.0f;
+      const float bv = col >= d ? Cf[16 * (col - d) + k] : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
     }
   }
-  for (int w = 0; w < nwave; ++w) {
-    if (wave == w) {
+  // lane holds Vm[4 kq + q][16 g + r] = V[256 g + 16 r + 4 kq + q]
 #pragma unroll
-      for (int g = 0; g < TRK_MAX_BINS / 256; ++g) {
-        if (g >= g16) continue;
+  for (int q = 0; q < 4; ++q) part[wave][16 * r + 4 * kq + q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < kTile) {
+    float sum = part[0][threadIdx.x];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = 4 * kq + q;
-          const int idx = 16 * (16 * g + r) + row;
-          if (idx < nbins) Vs[idx] += acc[g][q];
-        }
-      }
-    }
-    __syncthreads();
+    for (int w = 1; w < kConvWaves; ++w) sum += part[w][threadIdx.x];
+    const int i = kTile * g + threadIdx.x;
+    if (i < nbins) v[i] = static_cast<double>(sum);
   }
-  for (int m = threadIdx.x; m < nbins; m += blockDim.x) v[m] = static_cast<double>(Vs[m]);
-  if (threadIdx.x == 0 && wake_par != nullptr) {
-    wake_par[0] = smin;
-    wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
-  }
+  write_wake_par(smin, width, nbins, wake_par);
 }
 
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
                            double omega, int mode, double *v, double *wake_par, hipStream_t st) {
+  const int tiles = (nbins + kTile - 1) / kTile;
   if (mode == TRK_WAKE_FP32_MFMA)
-    hipLaunchKernelGGL(k_conv_mfma, dim3(1), dim3(1024), 0, st, counts, nbins, range, tau0, omega,
-                       v, wake_par);
+    hipLaunchKernelGGL(k_conv_mfma, dim3(tiles), dim3(64 * kConvWaves), 0, st, counts, nbins,
+                       range, tau0, omega, v, wake_par);
   else
-    hipLaunchKernelGGL(k_conv_fp64, dim3(1), dim3(1024), 0, st, counts, nbins, range, tau0, omega,
-                       v, wake_par);
+    hipLaunchKernelGGL(k_conv_fp64, dim3(tiles), dim3(kTile), 0, st, counts, nbins, range, tau0,
+                       omega, v, wake_par);
   return hipGetLastError();
 }
 
@@ -241,7 +259,7 @@ hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64
                             const double *v, const double *wake_par, int nbins, double kfac,
                             hipStream_t st) {
   const int64_t want = nblocks(n_total);
-  const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxGridStride ? kMaxGridStride : want));
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxRunGrid ? kMaxRunGrid : want));
   hipLaunchKernelGGL(k_wake_kick, dim3(grid), dim3(kBlock), 0, st, s, dp, n_alive, v, wake_par,
                      nbins, kfac);
   return hipGetLastError();

@@ -62,10 +62,11 @@ __device__ __forceinline__ double cos_kernel(double r) {
   return fma(r2, p, 1.0);
 }
 
+// |x| < 2^31 pi/2: the quadrant count fits an int
 __device__ __forceinline__ double reduce_half_pi(double x, int &q) {
   const double k = __builtin_rint(x * kTwoOverPi);
   const double r = ((x - k * kPio2Hi) - k * kPio2Mid) - k * kPio2Lo;
-  q = static_cast<int>(static_cast<long long>(k) & 3);
+  q = static_cast<int>(k) & 3;
   return r;
 }
 
@@ -80,6 +81,17 @@ __device__ __forceinline__ double own_cos(double x) {
   const double r = reduce_half_pi(x, q);
   const double v = (q & 1) ? sin_kernel(r) : cos_kernel(r);
   return ((q + 1) & 2) ? -v : v;
+}
+
+// sin and cos of one argument from one reduction (the same values as own_sin
+// and own_cos)
+__device__ __forceinline__ void own_sincos(double x, double &sn, double &cs) {
+  int q;
+  const double r = reduce_half_pi(x, q);
+  const double sk = sin_kernel(r), ck = cos_kernel(r);
+  const double a = (q & 1) ? ck : sk, b = (q & 1) ? sk : ck;
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
 }
 
 __device__ __forceinline__ double own_log(double x) {

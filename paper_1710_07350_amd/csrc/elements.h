@@ -35,7 +35,8 @@ __device__ __forceinline__ void edrift(double (&z)[6], double L) {
 }
 
 // thick-quad sparsity pattern: every listed coefficient is non-zero
-__device__ __forceinline__ void map_p1(double (&z)[6], const double *__restrict__ c) {
+template <class CP>
+__device__ __forceinline__ void map_p1(double (&z)[6], CP c) {
   const double x = z[0], xp = z[1], y = z[2], yp = z[3], s = z[4], d = z[5];
   const double xd = x * d, xpd = xp * d, yd = y * d, ypd = yp * d;
   double a;
@@ -59,7 +60,8 @@ __device__ __forceinline__ void map_p1(double (&z)[6], const double *__restrict_
 }
 
 // identity + R56 + T566 (a chicane)
-__device__ __forceinline__ void map_p2(double (&z)[6], const double *__restrict__ c) {
+template <class CP>
+__device__ __forceinline__ void map_p2(double (&z)[6], CP c) {
   const double s = z[4], d = z[5];
   z[0] = c[0] * z[0];
   z[1] = c[1] * z[1];
@@ -73,7 +75,8 @@ __device__ __forceinline__ void map_p2(double (&z)[6], const double *__restrict_
 }
 
 // any second-order map: coefficient tests are wave-uniform branches
-__device__ __forceinline__ void map_gen(double (&z)[6], const double *__restrict__ c) {
+template <class CP>
+__device__ __forceinline__ void map_gen(double (&z)[6], CP c) {
   double in[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) in[k] = z[k];
@@ -158,7 +161,8 @@ __device__ __forceinline__ void canon_drift(double (&z)[6], Canon &c, double dl)
   z[4] = fma(q, t / (c.opd + pz), z[4]);
 }
 
-__device__ __forceinline__ void kquad(double (&z)[6], const double *__restrict__ k, int nsteps) {
+template <class CP>
+__device__ __forceinline__ void kquad(double (&z)[6], CP k, int nsteps) {
   Canon c = canonical(z);
   for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
@@ -172,7 +176,8 @@ __device__ __forceinline__ void kquad(double (&z)[6], const double *__restrict__
   slopes(z, c);
 }
 
-__device__ __forceinline__ void csbend(double (&z)[6], const double *__restrict__ k, int nsteps) {
+template <class CP>
+__device__ __forceinline__ void csbend(double (&z)[6], CP k, int nsteps) {
   Canon c = canonical(z);
   const double iopd = 1.0 / c.opd;
   for (int st = 0; st < nsteps; ++st) {
@@ -199,12 +204,15 @@ __device__ __forceinline__ void csbend(double (&z)[6], const double *__restrict_
   slopes(z, c);
 }
 
-__device__ __forceinline__ void rfca(double (&z)[6], double hk, double phase, double volt,
-                                     double pin, double pout) {
+// a = ks/2: cos(phase + ks) - cos(phase) = -2 sin(a) (sin(phase) cos(a) + cos(phase) sin(a))
+__device__ __forceinline__ void rfca(double (&z)[6], double hk, double sph, double cph,
+                                     double volt, double pin, double inv_pout) {
   const double a = hk * z[4];
-  const double dc = (-2.0 * dm::own_sin(phase + a)) * dm::own_sin(a);
+  double sa, ca;
+  dm::own_sincos(a, sa, ca);
+  const double dc = (-2.0 * fma(sph, ca, cph * sa)) * sa;
   const double num = fma(z[5], pin, volt * dc);
-  z[5] = num / pout;
+  z[5] = num * inv_pout;
 }
 
 // V(s): linear between bin centres, constant beyond the first and last

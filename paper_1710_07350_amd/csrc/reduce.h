@@ -87,6 +87,51 @@ __device__ __forceinline__ void block_moment_row(double w, const double (&d)[6],
   __syncthreads();
 }
 
+// As block_moment_row for kP particles per thread: (count, sum z_k,
+// sum z_k z_l) over the alive ones, written to row[0..28).
+template <int kP>
+__device__ __forceinline__ void block_moment_row_multi(const bool (&al)[kP],
+                                                       const double (&z)[kP][6], double *row) {
+  __shared__ double part[kWaves][28];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int c = 0; c < 28; ++c) {
+    int k = 0, l = 0;
+    if (c >= 1 && c < 7) {
+      k = c - 1;
+    } else if (c >= 7) {
+      int r = c - 7;
+      while (r >= 6 - k) {
+        r -= 6 - k;
+        ++k;
+      }
+      l = k + r;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+      double zk = z[q][0], zl = z[q][0];
+#pragma unroll
+      for (int j = 1; j < 6; ++j) {
+        if (j == k) zk = z[q][j];
+        if (j == l) zl = z[q][j];
+      }
+      const double term = c == 0 ? 1.0 : (c < 7 ? zk : zk * zl);
+      if (al[q]) v += term;
+    }
+    v = wave_sum(v);
+    if (lane == 0) part[wave][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    double s = part[0][threadIdx.x];
+#pragma unroll
+    for (int w2 = 1; w2 < kWaves; ++w2) s += part[w2][threadIdx.x];
+    row[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void block_minmax(double &mn, double &mx) {
   __shared__ double pm[kWaves][2];
 #pragma unroll

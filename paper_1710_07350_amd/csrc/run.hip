@@ -19,104 +19,89 @@
 
 #include <utility>
 
-#include "elements.h"
+#include "apply.h"
 #include "reduce.h"
 
 namespace trk {
 
-// Rarely executed handlers stay out of line so that their registers do not
-// count against the hot element loop.
-__device__ __noinline__ void radkick_call(double &dp, double sigma, uint32_t pid, uint32_t gp,
-                                          uint32_t klo, uint32_t khi) {
-  dp = fma(sigma, dm::gauss(pid, gp, 2u, klo, khi), dp);
-}
-__device__ __noinline__ void map_gen_call(double (&z)[6], const double *__restrict__ c) {
-  el::map_gen(z, c);
-}
-
-template <uint32_t kFeat, bool kMom>
+// kP particles per thread, strided by the grid size so every load and store
+// stays coalesced; the kP particles go through each element together, so an
+// element record is read once per kP particles and the loads of all kP are
+// in flight at once.  Loads are issued for indices below the array length
+// before the device-side particle count arrives (they stay in bounds), so
+// the count's latency is not paid twice.  kLong: the run reads and writes
+// only s and delta (RF cavities, wake kicks, longitudinal maps), so only
+// those two coordinates are loaded and kept in registers.  The moments
+// variant uses kP = 1 and exactly one particle per thread (every thread
+// reaches the per-pass block reductions).
+template <uint32_t kFeat, bool kMom, int kP, bool kLong>
 __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
+  const ConstElems elems = (ConstElems)a.elems;
+  const ConstPool pool = (ConstPool)a.pool;
+  const ElemCtx cx{a.vc, a.nv, a.v0, a.wake_v, a.wake_par, a.seed_lo, a.seed_hi};
   const int64_t n = *a.n_alive;
   if (a.zero_buf != nullptr && blockIdx.x == 0)
     for (int i = threadIdx.x; i < a.zero_n; i += kBlock) a.zero_buf[i] = 0u;
 
   double smin = __builtin_huge_val(), smax = -__builtin_huge_val();
+  const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t stride = kMom ? 0 : static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t step = kMom ? 0 : nthr * kP;
+  const int64_t ntot = a.n_total;
 
-  // moments variant: exactly one particle per thread (every thread must reach
-  // the per-pass block reductions); otherwise a grid-stride loop
-  for (int64_t it = 0, i = first; kMom ? (it < 1) : (i < n); ++it, i += stride) {
-    const bool act = i < n;
-    double z[6];
+  for (int64_t it = 0, base = first; kMom ? (it < 1) : (base < ntot); ++it, base += step) {
+    double z[kP][6];
+    bool act[kP], alive[kP];
+    int64_t rec[kP];
+    uint32_t pid[kP];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) z[k] = (act && ((a.ldmask >> k) & 1u)) ? a.z[k][i] : 0.0;
-    const uint32_t pid = (act && ((a.ldmask >> 6) & 1u)) ? a.id[i] : 0u;
-    bool alive = act;
-    int64_t rec = -1;
-
+    for (int q = 0; q < kP; ++q) {
+      const int64_t i = base + q * nthr;
+      const bool inb = i < ntot;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const bool want = kLong ? (k >= 4) : ((a.ldmask >> k) & 1u) != 0;
+        z[q][k] = (inb && want) ? a.z[k][i] : 0.0;
+      }
+      pid[q] = (!kLong && inb && ((a.ldmask >> 6) & 1u)) ? a.id[i] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+      act[q] = base + q * nthr < n;
+      alive[q] = act[q];
+      rec[q] = -1;
+    }
     for (int p = 0; p < a.npass; ++p) {
       const uint32_t gp = static_cast<uint32_t>(a.pass0 + p);
       for (int e = a.e0; e < a.e1; ++e) {
-        const DevElem E = a.elems[e];
-        if (alive) {
-          const double *__restrict__ c = a.pool + E.off;
-          switch (E.kind) {
-            case K_EDRIFT: el::edrift(z, E.p0); break;
-            case K_MAP2_P1: el::map_p1(z, c); break;
-            case K_MAP2_P2: el::map_p2(z, c); break;
-            case K_MULT: el::mult(z, E.p0, E.ip); break;
-            case K_MAP2_GEN:
-              if constexpr ((kFeat & F_GEN) != 0) map_gen_call(z, c);
-              break;
-            case K_KQUAD:
-              if constexpr ((kFeat & F_KD) != 0) el::kquad(z, c, E.ip);
-              break;
-            case K_CSBEND:
-              if constexpr ((kFeat & F_KD) != 0) el::csbend(z, c, E.ip);
-              break;
-            case K_RFCA:
-              if constexpr ((kFeat & F_RF) != 0) {
-                const int v = p * a.nv + (E.vslot - a.v0);
-                el::rfca(z, E.p0, E.p1, E.p2, a.vc[v][0], a.vc[v][1]);
-              }
-              break;
-            case K_WAKE:
-              if constexpr ((kFeat & F_WAKE) != 0) {
-                const int v = p * a.nv + (E.vslot - a.v0);
-                const double vs =
-                    el::wake_interp(z[4], a.wake_par[0], a.wake_par[1], a.wake_v, E.ip);
-                z[5] = fma(-a.vc[v][0], vs, z[5]);
-              }
-              break;
-            case K_RADKICK:
-              if constexpr ((kFeat & F_RNG) != 0) radkick_call(z[5], E.p0, pid, gp, a.seed_lo, a.seed_hi);
-              break;
-            default: break;
-          }
-          if (E.aper != TRK_APER_NONE && el::aperture_lost(E.aper, E.a0, E.a1, z)) {
-            alive = false;
-            rec = static_cast<int64_t>((static_cast<uint64_t>(gp) << 32) | static_cast<uint32_t>(e));
-          }
-        }
+        const DevElem E = elems[e];
+#pragma unroll
+        for (int q = 0; q < kP; ++q)
+          apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
       }
       if constexpr (kMom) {
         double d[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) d[k] = alive ? z[k] - a.mom_shift[k] : 0.0;
+        for (int k = 0; k < 6; ++k) d[k] = alive[0] ? z[0][k] - a.mom_shift[k] : 0.0;
         double *row = a.mom_part + (static_cast<int64_t>(p) * gridDim.x + blockIdx.x) * 28;
-        block_moment_row(alive ? 1.0 : 0.0, d, row);
+        block_moment_row(alive[0] ? 1.0 : 0.0, d, row);
       }
     }
-    if (act) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if ((a.stmask >> k) & 1u) a.z[k][i] = z[k];
-      if (rec >= 0) a.lost_at[i] = rec;
-      if (alive) {
-        smin = fmin(smin, z[4]);
-        smax = fmax(smax, z[4]);
+    for (int q = 0; q < kP; ++q) {
+      if (!act[q]) continue;
+      const int64_t i = base + q * nthr;
+#pragma unroll
+      for (int k = kLong ? 4 : 0; k < 6; ++k)
+        if ((a.stmask >> k) & 1u) a.z[k][i] = z[q][k];
+      if (!kLong && rec[q] >= 0) a.lost_at[i] = rec[q];
+      if (alive[q]) {
+        smin = fmin(smin, z[q][4]);
+        smax = fmax(smax, z[q][4]);
       }
+    }
+    if constexpr (!kMom) {
+      if (base + nthr * kP >= n) break;  // nothing alive further on
     }
   }
   if (a.mm_part != nullptr) {
@@ -128,12 +113,55 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
   }
 }
 
+// light element families (no kick-drift, random or generic-map elements)
+// are memory bound: several particles per thread
+constexpr bool light(uint32_t f) { return (f & (F_KD | F_RNG | F_GEN)) == 0; }
+constexpr bool longit_ok(uint32_t f) { return (f & ~(F_RF | F_WAKE)) == 0; }
+
+template <uint32_t kFeat, bool kLong>
+void launch_ppt(const RunArgs &a, int grid, hipStream_t st) {
+  switch (a.ppt) {
+    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
+  }
+}
+
 template <uint32_t kFeat>
 void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
-  if (a.mom)
-    hipLaunchKernelGGL((k_run<kFeat, true>), dim3(grid), dim3(kBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_run<kFeat, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  if (a.mom) {
+    hipLaunchKernelGGL((k_run<kFeat, true, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  } else if constexpr (light(kFeat)) {
+    if constexpr (longit_ok(kFeat)) {
+      if (a.longit) {
+        launch_ppt<kFeat, true>(a, grid, st);
+        return;
+      }
+    }
+    launch_ppt<kFeat, false>(a, grid, st);
+  } else {
+    // heavy runs: one or two particles per thread
+    if (a.ppt >= 2)
+      hipLaunchKernelGGL((k_run<kFeat, false, 2, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_run<kFeat, false, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  }
+}
+
+int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req) {
+  const int64_t nb = nblocks(n_total);
+  if (a.mom) {
+    a.ppt = 1;
+    return static_cast<int>(nb < 1 ? 1 : nb);
+  }
+  int ppt = ppt_req > 0 ? ppt_req : (a.longit ? kLongPPT : (light(a.feat) ? kLightPPT : 1));
+  if (!light(a.feat)) ppt = ppt >= 2 ? 2 : 1;
+  ppt = ppt >= 8 ? 8 : (ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1));
+  a.ppt = ppt;
+  const int64_t want = (n_total + static_cast<int64_t>(kBlock) * ppt - 1) / (kBlock * ppt);
+  const int64_t cap = cap_req > 0 ? cap_req : (a.longit ? kLongRunGrid : kMaxRunGrid);
+  return static_cast<int>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
 template <uint32_t... kF>

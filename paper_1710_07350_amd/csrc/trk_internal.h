@@ -13,6 +13,10 @@ constexpr int kBlock = 256;        // threads per block of the particle kernels
 constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
 constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
+constexpr int kLightPPT = 4;       // particles per thread of memory-bound runs
+constexpr int kLongPPT = 2;        // ... of runs that touch only s and delta
+constexpr int kLongRunGrid = 2048; // grid-stride cap of those runs (8 blocks per CU)
+constexpr int kMaxRunGrid = 4096;  // grid-stride cap of the run kernel
 
 // Device element kinds after host-side classification.  MAP2 maps are
 // evaluated through one of three code paths with identical arithmetic:
@@ -53,9 +57,9 @@ static_assert(sizeof(DevElem) == 80, "DevElem layout");
 //   MAP2_GEN 168: C[6] R[6][6] T[6][21]
 //   KQUAD      7: kq[4] dl[3]
 //   CSBEND    23: kA[4] kB[4] cph[3] sph[3] vers[3] rs[3] dl[3]
-// Scalars: EDRIFT p0 = L; MULT p0 = KnL/n!; RFCA p0 = k/2, p1 = phase,
-//   p2 = V; RADKICK p0 = sigma; WAKE ip = nbins.
-// Pass-varying constants vc[slot] = (a, b): RFCA (P_in, P_out), WAKE (kfac, 0).
+// Scalars: EDRIFT p0 = L; MULT p0 = KnL/n!; RFCA p0 = k/2, p1 = sin(phase),
+//   p2 = cos(phase), p3 = V; RADKICK p0 = sigma; WAKE ip = nbins.
+// Pass-varying constants vc[slot] = (a, b): RFCA (P_in, 1/P_out), WAKE (kfac, 0).
 
 struct RunArgs {
   double *z[6];
@@ -70,7 +74,10 @@ struct RunArgs {
   uint32_t seed_lo, seed_hi;
   uint32_t ldmask, stmask;  // bit k: coordinate k loaded / stored; bit 6: id
   uint32_t feat;            // element families present (selects the instantiation)
-  int32_t pad_;
+  int32_t longit;           // run reads/writes only s and delta, no apertures
+  int32_t ppt;              // particles per thread (1, 2, 4, 8)
+  int32_t grid_cap;         // grid-stride cap
+  int64_t n_total;          // array length (bound of speculative loads)
   const double *wake_v;     // V[nbins] when elements[e0] is a WAKE
   const double *wake_par;   // (smin, 1/delta)
   double *mm_part;          // [gridDim.x][2] (min s, max s) of survivors, or null
@@ -81,6 +88,27 @@ struct RunArgs {
   const double *mom_shift;  // [6]
   double vc[kMaxVar][2];
 };
+
+// Batched launch over concatenated variants (see batch.hip).
+struct BatchArgs {
+  double *z[6];
+  uint32_t *id;
+  int64_t *lost_at;
+  const int64_t *seg_off;    // [nvar+1] particle offsets of the variants
+  const int64_t *chunk_off;  // [nvar+1] ticket offsets (chunks of kBlock*ppt particles)
+  const uint64_t *seeds;     // [nvar] random-kick keys
+  const DevElem *elems;      // [nvar][nelem]
+  const double *pool;
+  int32_t nelem, nvar, pass0, npass;
+  uint32_t ldmask, stmask;
+  uint32_t *ticket;          // zeroed before the launch
+  int64_t total;             // tickets
+  double *mom_part;          // [total][npass][28] or null
+};
+hipError_t launch_batch(const BatchArgs &a, uint32_t feat, int ppt, int grid, hipStream_t st);
+hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_off, int nvar,
+                                     int npass, double *out, int out_pass0, int out_passes,
+                                     hipStream_t st);
 
 // ---------------------------------------------------------------- workspace
 struct Workspace {
@@ -113,11 +141,15 @@ hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_tota
 hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
                             const double *mm_part, int mm_n, int nbins, uint32_t *counts,
                             double *range, hipStream_t st);
+// v: the convolution; wake_par: (smin, nbins/width) or null
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
                            double omega, int mode, double *v, double *wake_par, hipStream_t st);
 hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64_t n_total,
                             const double *v, const double *wake_par, int nbins, double kfac,
                             hipStream_t st);
+// launch shape of a run: fills a.ppt and returns the grid (a.longit, a.feat,
+// a.mom set; ppt_req/cap_req 0 = automatic)
+int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req);
 hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_t n_total,
                               const double *shift, double *part, int grid, hipStream_t st);
 hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const double *shift,
