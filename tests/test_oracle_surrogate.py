@@ -1,0 +1,290 @@
+"""Pins of the surrogate oracle: bfloat16 rounding against torch's own
+conversion, the network and its gradient against torch autograd and central
+finite differences, Adam against closed forms and torch.optim.Adam, the
+section's linear map against symplecticity and linearity, the Twiss
+parameters against their defining invariants, and the gate against plain
+tracking (no admitted particle is lost)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from paper_1710_07350_amd import inputs
+
+SIG = np.array(inputs.BEAM_SIGMAS)
+HW = 6.0 * SIG
+# central-difference step of the linear map, relative to the box half width:
+# the best balance of truncation (sextupoles) and rounding (the bend's
+# polar-frame update cancels terms of ~6 cm) on this section
+H_REL = 1e-4
+
+
+# ---------------------------------------------------------------- bfloat16
+def test_bf16_rne_matches_torch_conversion():
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(200000) * np.exp(rng.uniform(-20, 20, 200000))).astype(np.float32)
+    # exact ties: low 16 bits 0x8000 with even and odd kept parts
+    bits = rng.integers(0x3F800000, 0x40800000, 2000, dtype=np.uint64).astype(np.uint32)
+    ties = ((bits & 0xFFFF0000) | 0x8000).astype(np.uint32).view(np.float32)
+    x = np.concatenate([x, ties, -ties, np.float32([0.0, -0.0, 1.0, 65504.0, 1e-30])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    got = S.bf16_rne(x)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_split_bf16x2_carries_sixteen_bits():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(100000).astype(np.float32)
+    hi, lo = S.split_bf16x2(x)
+    assert np.array_equal(hi, S.bf16_rne(hi)) and np.array_equal(lo, S.bf16_rne(lo))
+    err = np.abs(x.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64))
+    assert (err <= np.abs(x) * 2.0 ** -16).all()
+    assert (np.abs(lo) <= np.abs(x) * 2.0 ** -8).all()
+
+
+# ---------------------------------------------------------------- network
+def torch_net(p64: np.ndarray):
+    P = {k: torch.from_numpy(np.array(v, dtype=np.float64)).requires_grad_(True)
+         for k, v in S.unpack(p64.copy()).items()}
+
+    def f(u):
+        u = u.clone()
+        u[:, S.S_COORD] = 0.0
+        h1 = torch.nn.functional.silu(torch.nn.functional.linear(u, P["W1"], P["b1"]))
+        h2 = h1 + torch.nn.functional.silu(torch.nn.functional.linear(h1, P["W2"], P["b2"]))
+        h3 = h2 + torch.nn.functional.silu(torch.nn.functional.linear(h2, P["W3"], P["b3"]))
+        return torch.nn.functional.linear(h3, P["W4"], P["b4"])
+    return f, P
+
+
+def test_param_count():
+    assert S.N_PARAM == 134918
+
+
+def test_forward_matches_torch():
+    p = S.init_params(1).astype(np.float64)
+    P = S.unpack(p)
+    rng = np.random.default_rng(5)
+    for k in P:                       # non-zero biases exercise every term
+        if k.startswith("b"):
+            P[k][...] = rng.uniform(-0.3, 0.3, P[k].shape)
+    u = rng.uniform(-1, 1, (64, 6))
+    o = S.forward(p, u, "exact", round_weights=False)
+    f, _ = torch_net(p)
+    ref = f(torch.from_numpy(u)).detach().numpy()
+    np.testing.assert_allclose(o, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_forward_rounds_weights_to_bf16():
+    p = S.init_params(2)
+    u = np.random.default_rng(6).uniform(-1, 1, (16, 6))
+    q = S.bf16_rne(p).astype(np.float64)       # every entry rounded, biases too
+    P = S.unpack(q)
+    for k in ("b1", "b2", "b3", "b4"):
+        P[k][...] = S.unpack(p)[k]
+    a = S.forward(p, u, "exact", round_weights=True)
+    b = S.forward(q, u, "exact", round_weights=False)
+    assert np.array_equal(a, b)
+
+
+def test_gradient_matches_torch_autograd():
+    p = S.init_params(3).astype(np.float64)
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-1, 1, (32, 6))
+    t = rng.standard_normal((32, 6)) * 0.1
+    loss, g = S.loss_and_grad(p, u, t, round_weights=False)
+    f, P = torch_net(p)
+    L = ((f(torch.from_numpy(u)) - torch.from_numpy(t)) ** 2).sum() / (6 * 32)
+    L.backward()
+    ref = np.concatenate([P[k].grad.numpy().reshape(-1) for k, _ in S.SHAPES])
+    assert loss == pytest.approx(float(L.detach()), rel=1e-13)
+    np.testing.assert_allclose(g, ref, rtol=1e-11, atol=1e-16)
+
+
+def test_gradient_matches_central_differences():
+    p = S.init_params(4).astype(np.float64)
+    P = S.unpack(p)
+    rng = np.random.default_rng(8)
+    for k in P:
+        if k.startswith("b"):
+            P[k][...] = rng.uniform(-0.2, 0.2, P[k].shape)
+    u = rng.uniform(-1, 1, (16, 6))
+    t = rng.standard_normal((16, 6)) * 0.1
+    _, g = S.loss_and_grad(p, u, t, round_weights=False)
+    idx = np.concatenate([rng.choice(S.N_PARAM, 300, replace=False),
+                          [0, 1540, 1791, S.N_PARAM - 1, S.N_PARAM - 7]])
+    h = 1e-6
+    for i in idx:
+        q = p.copy()
+        q[i] += h
+        lp, _ = S.loss_and_grad(q, u, t, round_weights=False)
+        q[i] -= 2 * h
+        lm, _ = S.loss_and_grad(q, u, t, round_weights=False)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(abs(g[i]), 1e-4), (i, fd, g[i])
+
+
+def test_structural_zeros():
+    """s never enters (its W1 column has zero gradient) and the delta output
+    receives no gradient when its target and weights are zero."""
+    p = S.init_params(5).astype(np.float64)
+    rng = np.random.default_rng(9)
+    u = rng.uniform(-1, 1, (32, 6))
+    t = rng.standard_normal((32, 6)) * 0.1
+    t[:, S.D_COORD] = 0.0
+    _, g = S.loss_and_grad(p, u, t, round_weights=False)
+    G = S.unpack(g)
+    assert (G["W1"][:, S.S_COORD] == 0.0).all()
+    u2 = u.copy()
+    u2[:, S.S_COORD] = rng.uniform(-1, 1, 32)
+    assert np.array_equal(S.forward(p, u, "bf16x2"), S.forward(p, u2, "bf16x2"))
+
+
+def test_bf16_modes_are_close_to_exact():
+    p = S.init_params(6)
+    u = np.random.default_rng(10).uniform(-1, 1, (256, 6))
+    e = S.forward(p, u, "exact")
+    x2 = S.forward(p, u, "bf16x2")
+    x1 = S.forward(p, u, "bf16")
+    scale = np.abs(e).max()
+    assert np.abs(x2 - e).max() <= 1e-4 * scale
+    assert 1e-4 * scale < np.abs(x1 - e).max() <= 3e-2 * scale
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(1000).astype(np.float32)
+    g = rng.standard_normal(1000).astype(np.float32)
+    z = np.zeros(1000, np.float32)
+    lr = 1e-3
+    w1, m1, v1 = S.adam(w, z, z, g, 1, lr)
+    g64 = g.astype(np.float64)
+    ref = w.astype(np.float64) - lr * g64 / (np.abs(g64) + 1e-8)
+    np.testing.assert_allclose(w1, ref, rtol=2e-7, atol=1e-9)
+    np.testing.assert_allclose(m1, 0.1 * g64, rtol=1e-6)
+
+
+def test_adam_constant_gradient_moves_linearly():
+    w = np.float32([0.5, -2.0, 3.0])
+    g = np.float32([0.25, -1.0, 4.0])
+    m = np.zeros(3, np.float32)
+    v = np.zeros(3, np.float32)
+    lr = 1e-4
+    for t in range(1, 201):
+        w, m, v = S.adam(w, m, v, g, t, lr)
+    ref = np.float64([0.5, -2.0, 3.0]) - 200 * lr * np.sign(g)
+    # w is stored in binary32: each of the 200 steps rounds it by <= half an ulp
+    tol = 200 * 0.5 * np.spacing(np.abs(w)).astype(np.float64) + 1e-9
+    assert (np.abs(w - ref) <= tol).all()
+
+
+def test_adam_matches_torch_optim():
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal(500).astype(np.float32)
+    m = np.zeros(500, np.float32)
+    v = np.zeros(500, np.float32)
+    tw = torch.from_numpy(w.astype(np.float64)).requires_grad_(True)
+    opt = torch.optim.Adam([tw], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for t in range(1, 6):
+        g = rng.standard_normal(500).astype(np.float32)
+        w, m, v = S.adam(w, m, v, g, t, 3e-3)
+        tw.grad = torch.from_numpy(g.astype(np.float64))
+        opt.step()
+    np.testing.assert_allclose(w, tw.detach().numpy(), rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- linear map
+def section():
+    return inputs.ring_lattice(seed=0)[:100]
+
+
+def to_canon(z):
+    x, xp, y, yp, s, d = z
+    f = (1.0 + d) / math.sqrt(1.0 + xp * xp + yp * yp)
+    return np.array([x, xp * f, y, yp * f, -s, d])
+
+
+def test_section_linear_map_is_symplectic(orc):
+    C, R = S.linear_map(orc, section(), HW, H_REL)
+    # canonical Jacobian: d canon / d slopes at the output point C, times R,
+    # times the inverse of the same at the input origin
+    Jout = np.zeros((6, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = 1e-7
+        Jout[:, k] = (to_canon(C + e) - to_canon(C - e)) / 2e-7
+    Jin = np.diag([1.0, 1.0, 1.0, 1.0, -1.0, 1.0])
+    M = Jout @ R @ np.linalg.inv(Jin)
+    J = np.zeros((6, 6))
+    for i in range(3):
+        J[2 * i, 2 * i + 1], J[2 * i + 1, 2 * i] = 1.0, -1.0
+    assert np.abs(M.T @ J @ M - J).max() < 1e-7
+    # delta passes unchanged; s does not act on anything
+    assert np.array_equal(R[5], [0, 0, 0, 0, 0, 1.0]) and C[5] == 0.0
+    assert np.array_equal(R[[0, 1, 2, 3, 5], 4], np.zeros(5)) and abs(R[4, 4] - 1.0) < 1e-9
+
+
+def test_section_linear_map_is_the_first_order_part(orc):
+    C, R = S.linear_map(orc, section(), HW, H_REL)
+    rng = np.random.default_rng(13)
+    v = rng.uniform(-1, 1, 6) * HW
+    errs = []
+    for eps in (1e-3, 5e-4):
+        z = np.stack([eps * v, np.zeros(6)], axis=1)
+        b = orc.Beam(z, np.arange(2, dtype=np.uint32), np.full(2, -1, np.int64))
+        orc.track(b, section(), 1)
+        errs.append(np.abs(b.z[:, 0] - C - R @ (eps * v)).max())
+    # the remainder is second order: halving eps quarters it
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+# ---------------------------------------------------------------- gate
+_PARTIAL = []
+
+
+def partial_maps(orc):
+    """Linear maps from the section entrance to every element exit."""
+    if not _PARTIAL:
+        sec = section()
+        _PARTIAL.extend(S.linear_map(orc, sec[:k + 1], HW, H_REL)[1] for k in range(len(sec)))
+    return _PARTIAL
+
+
+def test_twiss_invariants(orc):
+    C, R = S.linear_map(orc, section(), HW, H_REL)
+    for i in (0, 2):
+        a, b, g, eta, etap = S.twiss(R, i)
+        # beta gamma - alpha^2 = det of the block = 1 up to the difference error
+        assert b > 0 and abs(b * g - a * a - 1.0) < 1e-7
+        T = np.array([[b, -a], [-a, g]])
+        M = R[i:i + 2, i:i + 2]
+        np.testing.assert_allclose(M @ T @ M.T, T, rtol=1e-7, atol=1e-9)
+        if i == 0:
+            np.testing.assert_allclose(M @ [eta, etap] + R[i:i + 2, 5], [eta, etap],
+                                       rtol=1e-9, atol=1e-12)
+    # the last partial map is the section map itself
+    assert np.array_equal(partial_maps(orc)[-1], R)
+
+
+def test_gate_admits_only_survivors(orc):
+    C, R = S.linear_map(orc, section(), HW, H_REL)
+    g = S.gate_constants(R, partial_maps(orc), HW, 0.4, 10e-3, 5e-3)
+    n = 100000
+    z = inputs.uniform_box_beam(n, seed=21, half_widths=HW)["z"]
+    adm = S.gate(z, g)
+    assert 0.002 < adm.mean() < 0.05
+    b = orc.Beam(z[:, adm], np.arange(int(adm.sum()), dtype=np.uint32),
+                 np.full(int(adm.sum()), -1, np.int64))
+    orc.track(b, section(), 1)
+    assert (b.lost_at < 0).all()
+    # a larger margin admits a subset
+    g2 = S.gate_constants(R, partial_maps(orc), HW, 0.5, 10e-3, 5e-3)
+    adm2 = S.gate(z, g2)
+    assert (adm2 <= adm).all() and adm2.sum() < adm.sum()
+    # the box: outside +-hw is never admitted, whatever the amplitude
+    z2 = np.zeros((6, 3))
+    z2[5] = [1.01 * HW[5], -1.01 * HW[5], 0.1 * HW[5]]
+    assert list(S.gate(z2, g)) == [False, False, True]
