@@ -28,9 +28,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a copy kernel of known size); None until measured for
-# the current kernel.
-TRAFFIC_PER_LAUNCH = {}
+# WRITE_SIZE (FETCH_SIZE scaled by 2.000, WRITE_SIZE by 1.000, the factors a
+# 1 GiB copy gives), averaged over the runs of one pass
+# (profiles/k_run_bunch_compressor_4e6_hbm_bytes.md); absent until measured
+# for the current kernel.
+TRAFFIC_PER_LAUNCH = {"bc": 99826187}
 
 
 def parse():
