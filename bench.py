@@ -13,7 +13,13 @@ Prints one JSON line with the throughput, the roofline position of the
 dominant kernel (the fused element-run kernel, timed with HIP events on its
 stream during the timed steps) and the CPU oracle timed on a bounded sample.
 
-  python bench.py [--steps K] [--warmup W] [--workload bc|ring|fodo|roof]
+  python bench.py [--steps K] [--warmup W] [--workload bc|ring|fodo|roof|surr]
+
+The surr workload measures the learned section surrogate instead: it trains
+the network on the GPU (pairs from the tracker over the admitted part of the
++-6 sigma box), then times one pass through the first ten ring cells with
+plain tracking and with gate + network + fallback on 1e7 fresh particles,
+and reports the speed-up and the surrogate's error against the tracker.
 """
 import argparse
 import json
@@ -40,7 +46,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="bc", choices=["bc", "ring", "fodo", "roof"])
+    ap.add_argument("--workload", default="bc", choices=["bc", "ring", "fodo", "roof", "surr"])
+    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
+    ap.add_argument("--precision", default="bf16x2", choices=["bf16", "bf16x2"])
     ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -134,12 +142,135 @@ def element_steps(lattice, passes, n, lost_at, first_pass):
     return float(alive) * passes * nel + float((p * nel + e + 1).sum())
 
 
+def surrogate_bench(args):
+    """Train the section surrogate, then time plain tracking against
+    gate + network + fallback on fresh particles of two distributions."""
+    import torch
+    from paper_1710_07350_amd import binding as B
+    from paper_1710_07350_amd import inputs
+
+    torch.cuda.set_device(0)
+    n = int(args.particles or 10_000_000)
+    prec = B.MLP_BF16X2 if args.precision == "bf16x2" else B.MLP_BF16
+    margin, aper = 0.5, (10e-3, 5e-3)
+    hw = 6.0 * np.array(inputs.BEAM_SIGMAS)
+    sec = inputs.ring_lattice(seed=0)[:100]
+    L = B.Lattice(sec)
+    sur = B.Surrogate(L, hw, margin, aper)
+    ws = sur.workspace(n)
+    # training pairs: n admitted inputs from the sampler, tracked through the section
+    t0 = time.perf_counter()
+    beam = B.Beam.empty(n)
+    B.surrogate_sample(sur, 5, 0, beam, ws)
+    u, r, npairs_t = B.surrogate_pairs(sur, beam, ws)
+    npairs = int(npairs_t.item())
+    D = B.surrogate_fit_scale(sur, r, npairs, ws)
+    del beam
+    t_pairs = time.perf_counter() - t0
+    print(f"pairs: {npairs} in {t_pairs:.2f} s; D = {D}", file=sys.stderr, flush=True)
+    inv = [1.0 / v if v > 0 else 0.0 for v in D]
+    m = B.Mlp(inputs.mlp_init_params(21))
+    batch = 8192
+    mws = B.mlp_workspace(batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = B.mlp_train(m, u, r, inv, mws, batch=batch, epochs=args.epochs, lr0=2e-3,
+                       lr_min=1e-5, seed=9, precision=prec, n_pairs=npairs).cpu().numpy()
+    t_train = time.perf_counter() - t0
+    print(f"training: {args.epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3e} -> "
+          f"{loss[-1]:.3e}", file=sys.stderr, flush=True)
+    del u, r
+
+    def one_set(d, name, reps=5):
+        src = B.Beam.from_inputs(d)
+        work = src.clone()
+        tws = B.Workspace(n)
+        times = {"plain": [], "surr": []}
+        B.profile_enable(True)
+        for rep in range(reps + 1):
+            for mode in ("plain", "surr"):
+                work.copy_(src)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                if mode == "plain":
+                    B.track(work, L, 1, tws)
+                else:
+                    B.surrogate_apply(sur, m, work, ws, precision=prec)
+                b.record()
+                torch.cuda.synchronize()
+                if rep > 0:
+                    times[mode].append(a.elapsed_time(b))
+                if rep == reps:
+                    if mode == "plain":
+                        ref = work.host()
+                    else:
+                        got = work.host()
+        infer_ms, infer_n = B.profile_read(1)
+        B.profile_enable(False)
+        # surrogate error on admitted particles against the tracker, by id
+        nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
+        work.copy_(src)
+        adm = B.surrogate_gate(sur, work).cpu().numpy().astype(bool)
+        ids = d["id"][adm]
+        pos_r = np.empty(n, np.int64)
+        pos_r[ref["id"]] = np.arange(n)
+        pos_g = np.empty(n, np.int64)
+        pos_g[got["id"]] = np.arange(n)
+        zr = ref["z"][:, pos_r[ids]]
+        zg = got["z"][:, pos_g[ids]]
+        lost_adm = int((ref["lost_at"][pos_r[ids]] >= 0).sum())
+        err = np.abs(zg - zr)
+        names = ["x", "xp", "y", "yp", "s", "dp"]
+        tp = float(np.median(times["plain"]))
+        ts = float(np.median(times["surr"]))
+        steps = element_steps(sec, 1, n, ref["lost_at"], 0)
+        out = {"set": name, "particles": n, "admitted": int(adm.sum()),
+               "admitted_lost_in_tracking": lost_adm,
+               "ms_plain": round(tp, 3), "ms_surrogate": round(ts, 3),
+               "speedup": round(tp / ts, 3),
+               "steps_per_s_plain": steps / (tp / 1e3),
+               "max_abs_error": {k: float(err[i].max()) if err.size else 0.0
+                                 for i, k in enumerate(names)},
+               "rms_error": {k: float(np.sqrt((err[i] ** 2).mean())) if err.size else 0.0
+                             for i, k in enumerate(names)},
+               "infer_ms": infer_ms / max(infer_n, 1)}
+        print(json.dumps(out), file=sys.stderr, flush=True)
+        return out
+
+    box = one_set(inputs.uniform_box_beam(n, seed=61, half_widths=hw), "uniform +-6 sigma box")
+    gauss = one_set(inputs.gaussian_beam(n, seed=62), "Gaussian ring beam")
+    flops = 2.0 * (6 * 256 + 2 * 256 * 256 + 256 * 6)
+    ach = box["admitted"] * flops / (box["infer_ms"] / 1e3) / 1e12
+    mx = box["max_abs_error"]
+    out = {"metric": "surrogate speedup over plain tracking of the section",
+           "value": box["speedup"], "unit": "x", "n_gpus": 1, "steps": 5, "warmup": 1,
+           "ms_per_step": box["ms_surrogate"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16 network (" + args.precision + " activations), "
+                                              "f64 linear part and fallback",
+           "data": "synthetic",
+           "config": {"workload": "learned surrogate of ring cells 0-9 (100 elements), "
+                                  f"1e7 fresh particles, gate margin {margin}",
+                      "training_pairs": npairs, "epochs": args.epochs, "batch": batch,
+                      "train_s": round(t_train, 2), "final_loss": float(loss[-1])},
+           "error": {"max_m": max(mx["x"], mx["y"], mx["s"]), "max_rad": max(mx["xp"], mx["yp"]),
+                     "meets_1e-6": max(mx.values()) <= 1e-6},
+           "sets": [box, gauss],
+           "roofline": {"bound": "mfma", "kernel": "trk::k_surr_infer", "achieved": round(ach, 2),
+                        "peak": 2500.0, "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4),
+                        "traffic": None}}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this "
               "single-GPU build (the sharded design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "surr":
+        return surrogate_bench(args)
     import torch
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs

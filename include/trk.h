@@ -229,6 +229,152 @@ int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes, int32_
                       const trk_batch_tuning *tune, double *moments_dev, void *workspace,
                       size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------ surrogate
+ * Learned surrogate of a fixed lattice section (an extension beyond the
+ * paper, which tracks element by element throughout; the linear part is the
+ * paper's first-order transfer matrix, Sec. 3 "matrix" elements):
+ *
+ *   y = C + R z + D * o(N(z)),
+ *
+ * C = map(0) and R = Jacobian of the section map at the origin (central
+ * differences of the tracker), N(z)_k = z_k / hw_k (box half widths; s is not
+ * an input), D_k = RMS of the residual y - (C + R z) over the training pairs
+ * (D = 0 for delta, which the section leaves unchanged), and o the residual
+ * network 6 -> 256 -> 256 -> 256 -> 6: h1 = silu(W1 u + b1),
+ * h2 = h1 + silu(W2 h1 + b2), h3 = h2 + silu(W3 h2 + b3), o = W4 h3 + b4,
+ * silu(a) = a / (1 + exp(-a)).  Matrix products run on bfloat16 matrix cores
+ * with FP32 accumulation: weights rounded to bfloat16 (nearest even) from an
+ * FP32 master copy, activations entered as one bfloat16 (TRK_MLP_BF16) or as
+ * the sum of two (TRK_MLP_BF16X2, 16 significant bits).
+ *
+ * Parameter vector (FP32, TRK_MLP_NPARAM): W1[256][6], b1[256], W2[256][256],
+ * b2[256], W3[256][256], b3[256], W4[6][256], b4[6]; W[out][in]. */
+#define TRK_MLP_IN 6
+#define TRK_MLP_HID 256
+#define TRK_MLP_OUT 6
+#define TRK_MLP_NPARAM 134918
+enum trk_mlp_precision { TRK_MLP_BF16 = 0, TRK_MLP_BF16X2 = 1 };
+
+typedef struct trk_mlp trk_mlp;
+/* copies params_host[TRK_MLP_NPARAM]; Adam moments zero, step count 0 */
+int trk_mlp_create(const float *params_host, trk_mlp **out);
+void trk_mlp_destroy(trk_mlp *m);
+/* copies the master parameters to the host (synchronises the stream) */
+int trk_mlp_get_params(const trk_mlp *m, float *params_host, void *stream);
+
+/* o = network(u) for n rows: u_dev[n][8] FP32 (columns 0..5, column 4 = s is
+ * ignored), out_dev[n][8] FP32 (columns 0..5; 6, 7 written as 0). */
+int trk_mlp_forward(const trk_mlp *m, const float *u_dev, int64_t n, float *out_dev,
+                    int32_t precision, void *stream);
+
+/* workspace of the training calls for batches of up to `batch` rows */
+size_t trk_mlp_workspace_size(int32_t batch);
+
+/* Gradient of L = (1/(6n)) sum_rows sum_k (o_k - t_k)^2 over the n rows of
+ * u_dev[n][8] with targets t_dev[n][8] (FP32; columns 0..5), n a multiple of
+ * 64: forward in `precision` (values saved for the backward pass), backward
+ * with bfloat16 operands and FP32 accumulation, weight gradients as split-K
+ * partials summed in a fixed order.  grad_dev[TRK_MLP_NPARAM] FP32 (layout
+ * of the parameter vector); loss_dev: NULL or one float receiving L. */
+int trk_mlp_backward(const trk_mlp *m, const float *u_dev, const float *t_dev, int32_t n,
+                     int32_t precision, float *grad_dev, float *loss_dev, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba 2015) with beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8 on the master parameters, from grad_dev[TRK_MLP_NPARAM]:
+ * m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ * w <- w - lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps), evaluated in binary64
+ * on binary32 state; t is the handle's step count, incremented first. */
+int trk_mlp_adam_step(trk_mlp *m, const float *grad_dev, double lr, void *stream);
+
+/* Training: epochs over n_pairs pairs u_dev[n][8], r_dev[n][8] (FP32) with
+ * targets t_k = r_k inv_scale[k]; each epoch visits the pairs in the order
+ * (a i + c) mod n_pairs (a, c drawn from `seed`, a coprime with n_pairs) in
+ * batches of `batch` rows (the remainder is dropped), one Adam step per
+ * batch, learning rate lr_min + (lr0 - lr_min)(1 + cos(pi step/steps))/2.
+ * loss_dev: NULL or [epochs] floats, the sum over the epoch's batches of the
+ * batch loss, divided by the number of batches. */
+typedef struct trk_train_opts {
+  int32_t batch;      /* rows per step, a multiple of 64 */
+  int32_t epochs;
+  int32_t precision;  /* forward precision while training */
+  int32_t reserved;
+  double lr0, lr_min;
+  uint64_t seed;
+} trk_train_opts;
+int trk_mlp_train(trk_mlp *m, const float *u_dev, const float *r_dev, int64_t n_pairs,
+                  const double inv_scale[6], const trk_train_opts *opts, float *loss_dev,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* A surrogate handle for a section lattice (no TRK_RFCA, TRK_WAKE, TRK_RADKICK
+ * or TRK_MAP2 elements; the lattice must outlive the handle).  Creation
+ * tracks 13 probes (the origin and +-h_rel hw_k along each coordinate)
+ * through the section and through each of its element prefixes with the
+ * tracker (synchronising `stream`) and computes on the host:
+ *   C, R (central differences), the periodic Courant--Snyder parameters of
+ *   the x and y blocks of R, the periodic dispersion, and the largest beta_x,
+ *   beta_y, |eta| over the section's element exits (prefix maps).
+ * Gate: a particle is admitted iff |z_k| <= hw_k for k != s and
+ *   (xhat/a)^2 + (yhat/b)^2 <= (1 - margin)^2, xhat = sqrt(J_x betahat_x) +
+ *   etahat |delta|, yhat = sqrt(J_y betahat_y), J the linear invariants of
+ *   the betatron parts (each operation a separate binary64 rounding). */
+typedef struct trk_surrogate_opts {
+  double half_width[6];  /* training box half widths (centred at 0) */
+  double margin;         /* gate margin in [0, 1) */
+  double h_rel;          /* central-difference step / half width (0: 1e-4) */
+  double aper_a, aper_b; /* semi-axes of the section's elliptical aperture [m] */
+} trk_surrogate_opts;
+typedef struct trk_surrogate_info {
+  double C[6], R[36], D[6];
+  double alpha_x, beta_x, gamma_x, eta, etap, alpha_y, beta_y, gamma_y;
+  double beta_hat_x, beta_hat_y, eta_hat, lim;
+  double sample_half_width[6]; /* box of the sampler (contains the admitted set) */
+} trk_surrogate_info;
+typedef struct trk_surrogate trk_surrogate;
+int trk_surrogate_create(const trk_lattice *section, const trk_surrogate_opts *opts, void *stream,
+                         trk_surrogate **out);
+void trk_surrogate_destroy(trk_surrogate *s);
+int trk_surrogate_get_info(const trk_surrogate *s, trk_surrogate_info *out);
+
+/* workspace of the calls below for beams of up to n_total particles */
+size_t trk_surrogate_workspace_size(const trk_surrogate *s, int64_t n_total);
+
+/* admit_dev[i] = 1 if particle i < *n_alive is admitted, else 0 */
+int trk_surrogate_gate(const trk_surrogate *s, const trk_beam *beam, uint8_t *admit_dev,
+                       void *stream);
+
+/* Fills beam (n_total slots; ids 0.., lost_at -1, *n_alive = n_total) with
+ * admitted points drawn uniformly: candidate c = first, first+1, ... takes
+ * two Philox4x32-10 blocks with counters (c_lo, c_hi, 5, 0) and
+ * (c_lo, c_hi, 5, 1), key = seed; z_k = (2 u_k - 1) w_k with
+ * u_k = (word_k + 1/2) 2^-32, w = sample_half_width; admitted candidates are
+ * kept in candidate order.  *next_out (host) = first candidate not examined.
+ * Synchronises the stream once per round of candidates. */
+int trk_surrogate_sample(const trk_surrogate *s, uint64_t seed, uint64_t first, trk_beam *beam,
+                         uint64_t *next_out, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Training pairs: the admitted particles of `beam` (in their order) are
+ * tracked through the section; survivors j = 0 .. *n_pairs_dev - 1 give
+ * u_dev[j][8] = N(z_in) (FP32) and r_dev[j][8] = y - (C + R z_in) (FP32,
+ * columns 0..4).  The beam itself is not modified. */
+int trk_surrogate_pairs(const trk_surrogate *s, const trk_beam *beam, float *u_dev, float *r_dev,
+                        int64_t *n_pairs_dev, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* D_k = sqrt(mean over the n rows of r_k^2) for k = 0..4 (synchronises) */
+int trk_surrogate_fit_scale(trk_surrogate *s, const float *r_dev, int64_t n, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* One pass through the section for the alive particles of `beam`: admitted
+ * ones get the surrogate output (in place), the others are tracked element
+ * by element (pass index first_pass in their loss records); the beam is
+ * then compacted as trk_track leaves it.  n_admitted_dev: NULL or the
+ * number of admitted particles. */
+int trk_surrogate_apply(const trk_surrogate *s, const trk_mlp *m, trk_beam *beam,
+                        int32_t first_pass, int32_t precision, int64_t *n_admitted_dev,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------ test hooks
  * Bit-exactness probes of the device arithmetic used by the kernels.
  * fn: 0 sin, 1 cos, 2 log, 3 exp (own implementations), 4 sqrt, 5 x / y. */
@@ -245,7 +391,8 @@ int trk_gauss(const uint32_t *id_dev, uint32_t step, uint32_t tag, uint64_t seed
 const char *trk_status_string(int status);
 const char *trk_last_error(void);
 /* per-kernel-class device time (ms) and launch count accumulated with HIP
- * events while enabled; class 0 = fused element run. */
+ * events while enabled; class 0 = fused element run, class 1 = surrogate
+ * network inference. */
 int trk_profile_enable(int32_t on);
 int trk_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches);
 

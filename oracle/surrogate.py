@@ -61,20 +61,10 @@ def unpack(p: np.ndarray) -> Dict[str, np.ndarray]:
 
 
 def init_params(seed: int) -> np.ndarray:
-    """Uniform fan-in initialisation (|w| <= 1/sqrt(fan_in)), zero biases.
-    The s column of W1 and the delta row of W4 are zero: s does not enter
-    and delta is not predicted."""
-    rng = np.random.Generator(np.random.PCG64([seed, 5]))
-    p = np.zeros(N_PARAM, dtype=np.float32)
-    P = unpack(p)
-    for name, shp in SHAPES:
-        if name.startswith("W"):
-            lim = 1.0 / math.sqrt(shp[1])
-            P[name][...] = rng.uniform(-lim, lim, size=shp).astype(np.float32)
-    P["W1"][:, S_COORD] = 0.0
-    P["W4"][D_COORD, :] = 0.0
-    P["W4"] *= np.float32(0.1)
-    return p
+    """The seeded initial parameters (a shared input, not arithmetic of the
+    method): see paper_1710_07350_amd.inputs.mlp_init_params."""
+    from paper_1710_07350_amd import inputs
+    return inputs.mlp_init_params(seed)
 
 
 # ---------------------------------------------------------------- bfloat16
@@ -306,6 +296,62 @@ def gate(z: np.ndarray, g: dict) -> np.ndarray:
     uy = yh * g["inv_b"]
     q = ux * ux + uy * uy
     return box & (q <= g["lim"])
+
+
+def sample_widths(g: dict, a: float, b: float) -> np.ndarray:
+    """Half widths of the sampler's box, which contains every admitted point:
+    J_x <= a^2 lim / betahat_x, J_y <= b^2 lim / betahat_y and
+    |delta| <= a sqrt(lim) / etahat bound |x| <= sqrt(J_x beta_x) + |eta||delta|,
+    |x'| <= sqrt(J_x gamma_x) + |eta'||delta|, |y| <= sqrt(J_y beta_y),
+    |y'| <= sqrt(J_y gamma_y); each widened by 1e-6 relative and capped by the
+    training box."""
+    hw = g["hw"]
+    pad = 1.0 + 1e-6
+    lim = g["lim"]
+    jxm = ((a * a) * lim) / g["bhx"]
+    jym = ((b * b) * lim) / g["bhy"]
+    dm = (a * math.sqrt(lim)) / g["eh"] if g["eh"] > 0.0 else hw[5]
+    sw = [(math.sqrt(jxm * g["bx"]) + abs(g["eta"]) * dm) * pad,
+          (math.sqrt(jxm * g["gx"]) + abs(g["etap"]) * dm) * pad,
+          math.sqrt(jym * g["by"]) * pad,
+          math.sqrt(jym * g["gy"]) * pad,
+          hw[4],
+          dm * pad]
+    return np.array([min(sw[k], hw[k]) for k in range(6)])
+
+
+TAG_SAMPLE = 5
+
+
+def draw(orc, sw, seed: int, cand: int) -> np.ndarray:
+    """Candidate `cand` of the sampler: words of Philox4x32-10 at counters
+    (cand_lo, cand_hi, 5, 0) and (.., 1), key (seed_lo, seed_hi);
+    z_k = (2 u_k - 1) sw_k with u_k = (w_k + 1/2) 2^-32."""
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    lo, hi = cand & 0xFFFFFFFF, cand >> 32
+    w = orc.philox4x32_10((lo, hi, TAG_SAMPLE, 0), key) + orc.philox4x32_10((lo, hi, TAG_SAMPLE, 1), key)
+    z = np.empty(6)
+    for k in range(6):
+        u = (float(w[k]) + 0.5) * 2.0 ** -32
+        z[k] = (2.0 * u - 1.0) * sw[k]
+    return z
+
+
+def sample(orc, g: dict, sw, seed: int, first: int, n: int) -> Tuple[np.ndarray, int]:
+    """The first n admitted candidates from `first` on, in candidate order;
+    returns z[6][n] and the index of the last candidate examined plus one."""
+    out = []
+    c = first
+    while len(out) < n:
+        z = draw(orc, sw, seed, c)
+        if _gate_one(z, g):
+            out.append(z)
+        c += 1
+    return np.array(out).T, c
+
+
+def _gate_one(z, g) -> bool:
+    return bool(gate(np.asarray(z, dtype=np.float64).reshape(6, 1), g)[0])
 
 
 # ---------------------------------------------------------------- surrogate

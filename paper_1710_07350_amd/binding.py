@@ -28,7 +28,14 @@ EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "t
            "trk_compact_lost", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
            "trk_batch_create", "trk_batch_destroy", "trk_batch_workspace_size",
-           "trk_track_batched")
+           "trk_track_batched", "trk_mlp_create", "trk_mlp_destroy", "trk_mlp_get_params",
+           "trk_mlp_forward", "trk_mlp_workspace_size", "trk_mlp_backward", "trk_mlp_adam_step",
+           "trk_mlp_train", "trk_surrogate_create", "trk_surrogate_destroy",
+           "trk_surrogate_get_info", "trk_surrogate_workspace_size", "trk_surrogate_gate",
+           "trk_surrogate_sample", "trk_surrogate_pairs", "trk_surrogate_fit_scale",
+           "trk_surrogate_apply")
+MLP_NPARAM = 134918
+MLP_BF16, MLP_BF16X2 = 0, 1
 
 
 class TrkError(RuntimeError):
@@ -64,6 +71,26 @@ class Opts(C.Structure):
 class BatchTuning(C.Structure):
     _fields_ = [("ppt", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("passes_per_launch", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("lr0", C.c_double), ("lr_min", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class SurrOpts(C.Structure):
+    _fields_ = [("half_width", C.c_double * 6), ("margin", C.c_double), ("h_rel", C.c_double),
+                ("aper_a", C.c_double), ("aper_b", C.c_double)]
+
+
+class SurrInfo(C.Structure):
+    _fields_ = [("C", C.c_double * 6), ("R", C.c_double * 36), ("D", C.c_double * 6),
+                ("alpha_x", C.c_double), ("beta_x", C.c_double), ("gamma_x", C.c_double),
+                ("eta", C.c_double), ("etap", C.c_double), ("alpha_y", C.c_double),
+                ("beta_y", C.c_double), ("gamma_y", C.c_double), ("beta_hat_x", C.c_double),
+                ("beta_hat_y", C.c_double), ("eta_hat", C.c_double), ("lim", C.c_double),
+                ("sample_half_width", C.c_double * 6)]
 
 
 class Wake(C.Structure):
@@ -112,6 +139,29 @@ def lib():
         L.trk_batch_workspace_size.restype = sz
         L.trk_track_batched.argtypes = [vp, C.POINTER(BeamStruct), i32, i32,
                                         C.POINTER(BatchTuning), vp, vp, sz, vp]
+        L.trk_mlp_create.argtypes = [vp, C.POINTER(vp)]
+        L.trk_mlp_destroy.argtypes = [vp]
+        L.trk_mlp_destroy.restype = None
+        L.trk_mlp_get_params.argtypes = [vp, vp, vp]
+        L.trk_mlp_forward.argtypes = [vp, vp, i64, vp, i32, vp]
+        L.trk_mlp_workspace_size.argtypes = [i32]
+        L.trk_mlp_workspace_size.restype = sz
+        L.trk_mlp_backward.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, sz, vp]
+        L.trk_mlp_adam_step.argtypes = [vp, vp, d, vp]
+        L.trk_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(C.c_double), C.POINTER(TrainOpts),
+                                    vp, vp, sz, vp]
+        L.trk_surrogate_create.argtypes = [vp, C.POINTER(SurrOpts), vp, C.POINTER(vp)]
+        L.trk_surrogate_destroy.argtypes = [vp]
+        L.trk_surrogate_destroy.restype = None
+        L.trk_surrogate_get_info.argtypes = [vp, C.POINTER(SurrInfo)]
+        L.trk_surrogate_workspace_size.argtypes = [vp, i64]
+        L.trk_surrogate_workspace_size.restype = sz
+        L.trk_surrogate_gate.argtypes = [vp, C.POINTER(BeamStruct), vp, vp]
+        L.trk_surrogate_sample.argtypes = [vp, u64, u64, C.POINTER(BeamStruct), C.POINTER(u64),
+                                           vp, sz, vp]
+        L.trk_surrogate_pairs.argtypes = [vp, C.POINTER(BeamStruct), vp, vp, vp, vp, sz, vp]
+        L.trk_surrogate_fit_scale.argtypes = [vp, vp, i64, vp, sz, vp]
+        L.trk_surrogate_apply.argtypes = [vp, vp, C.POINTER(BeamStruct), i32, i32, vp, vp, sz, vp]
         _LIB = L
     return _LIB
 
@@ -185,6 +235,36 @@ class Beam:
     @classmethod
     def from_inputs(cls, d: dict, device="cuda") -> "Beam":
         return cls(d["z"], d["id"], d["lost_at"], device=device)
+
+    @classmethod
+    def empty(cls, n: int, device="cuda") -> "Beam":
+        """Device beam of n zeroed slots (ids 0..n-1, all alive), allocated on
+        the device without a host copy."""
+        import torch
+        b = cls.__new__(cls)
+        b.n = int(n)
+        b.z = torch.zeros((6, b.n), dtype=torch.float64, device=device)
+        b.id = torch.arange(b.n, dtype=torch.int64, device=device).to(torch.int32)
+        b.lost_at = torch.full((b.n,), -1, dtype=torch.int64, device=device)
+        b.n_alive = torch.tensor([b.n], dtype=torch.int64, device=device)
+        b._struct = None
+        return b
+
+    def clone(self) -> "Beam":
+        b = Beam.__new__(Beam)
+        b.n = self.n
+        b.z = self.z.clone()
+        b.id = self.id.clone()
+        b.lost_at = self.lost_at.clone()
+        b.n_alive = self.n_alive.clone()
+        b._struct = None
+        return b
+
+    def copy_(self, other: "Beam") -> None:
+        self.z.copy_(other.z)
+        self.id.copy_(other.id)
+        self.lost_at.copy_(other.lost_at)
+        self.n_alive.copy_(other.n_alive)
 
     def struct(self) -> BeamStruct:
         b = BeamStruct()
@@ -346,3 +426,149 @@ def track_batched(batch: Batch, beam: Beam, passes: int, ws, first_pass: int = 0
     _check(lib().trk_track_batched(batch.handle, C.byref(beam.struct()), passes, first_pass,
                                    C.byref(t), moments.data_ptr() if moments is not None else None,
                                    ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+
+
+# ------------------------------------------------------------------ surrogate
+class Mlp:
+    """Device copy of the residual network (FP32 master weights, Adam state,
+    bfloat16 copies)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (MLP_NPARAM,)
+        h = C.c_void_p()
+        _check(lib().trk_mlp_create(p.ctypes.data, C.byref(h)))
+        self.handle = h
+
+    def params(self, stream=None) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, dtype=np.float32)
+        _check(lib().trk_mlp_get_params(self.handle, out.ctypes.data, _stream_handle(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.trk_mlp_destroy(h)
+            self.handle = None
+
+
+def mlp_forward(m: Mlp, u, precision: int = MLP_BF16X2, stream=None):
+    """u: device float32 [n, 8] -> device float32 [n, 8]"""
+    import torch
+    out = torch.empty_like(u)
+    _check(lib().trk_mlp_forward(m.handle, u.data_ptr(), int(u.shape[0]), out.data_ptr(),
+                                 precision, _stream_handle(stream)))
+    return out
+
+
+def mlp_workspace(batch: int, device="cuda"):
+    import torch
+    return torch.empty(int(lib().trk_mlp_workspace_size(batch)), dtype=torch.uint8, device=device)
+
+
+def mlp_backward(m: Mlp, u, t, ws, precision: int = MLP_BF16X2, stream=None):
+    """Gradient (device float32 [NPARAM]) and loss (device float32 [1])."""
+    import torch
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=u.device)
+    loss = torch.empty(1, dtype=torch.float32, device=u.device)
+    _check(lib().trk_mlp_backward(m.handle, u.data_ptr(), t.data_ptr(), int(u.shape[0]), precision,
+                                  g.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(stream)))
+    return g, loss
+
+
+def mlp_adam_step(m: Mlp, grad, lr: float, stream=None) -> None:
+    _check(lib().trk_mlp_adam_step(m.handle, grad.data_ptr(), lr, _stream_handle(stream)))
+
+
+def mlp_train(m: Mlp, u, r, inv_scale, ws, batch: int, epochs: int, lr0: float, lr_min: float,
+              seed: int = 0, precision: int = MLP_BF16X2, n_pairs: Optional[int] = None,
+              stream=None):
+    """Returns the per-epoch mean batch loss (device float32 [epochs])."""
+    import torch
+    o = TrainOpts(batch, epochs, precision, 0, lr0, lr_min, seed)
+    sc = (C.c_double * 6)(*[float(v) for v in inv_scale])
+    loss = torch.zeros(max(epochs, 1), dtype=torch.float32, device=u.device)
+    n = int(u.shape[0]) if n_pairs is None else int(n_pairs)
+    _check(lib().trk_mlp_train(m.handle, u.data_ptr(), r.data_ptr(), n, sc, C.byref(o),
+                               loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return loss
+
+
+class Surrogate:
+    """Section handle: linear map, gate constants, residual scale."""
+
+    def __init__(self, section: Lattice, half_width, margin: float, aper=(10e-3, 5e-3),
+                 h_rel: float = 1e-4, stream=None):
+        o = SurrOpts()
+        for k in range(6):
+            o.half_width[k] = float(half_width[k])
+        o.margin, o.h_rel = float(margin), float(h_rel)
+        o.aper_a, o.aper_b = float(aper[0]), float(aper[1])
+        h = C.c_void_p()
+        _check(lib().trk_surrogate_create(section.handle, C.byref(o), _stream_handle(stream),
+                                          C.byref(h)))
+        self.handle = h
+        self.section = section                  # keep the lattice alive
+
+    def info(self) -> dict:
+        i = SurrInfo()
+        _check(lib().trk_surrogate_get_info(self.handle, C.byref(i)))
+        out = {k: getattr(i, k) for k, _ in SurrInfo._fields_}
+        out["C"] = np.array(list(i.C))
+        out["R"] = np.array(list(i.R)).reshape(6, 6)
+        out["D"] = np.array(list(i.D))
+        out["sample_half_width"] = np.array(list(i.sample_half_width))
+        return out
+
+    def workspace(self, n_total: int, device="cuda"):
+        import torch
+        nb = int(lib().trk_surrogate_workspace_size(self.handle, n_total))
+        return torch.empty(nb, dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.trk_surrogate_destroy(h)
+            self.handle = None
+
+
+def surrogate_gate(s: Surrogate, beam: Beam, stream=None):
+    import torch
+    adm = torch.zeros(max(beam.n, 1), dtype=torch.uint8, device=beam.z.device)
+    _check(lib().trk_surrogate_gate(s.handle, C.byref(beam.struct()), adm.data_ptr(),
+                                    _stream_handle(stream)))
+    return adm[:beam.n]
+
+
+def surrogate_sample(s: Surrogate, seed: int, first: int, beam: Beam, ws, stream=None) -> int:
+    nxt = C.c_uint64()
+    _check(lib().trk_surrogate_sample(s.handle, seed, first, C.byref(beam.struct()), C.byref(nxt),
+                                      ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return int(nxt.value)
+
+
+def surrogate_pairs(s: Surrogate, beam: Beam, ws, stream=None):
+    """(u [n, 8], r [n, 8], n_pairs device int64 [1]) for the beam's admitted particles."""
+    import torch
+    u = torch.zeros((max(beam.n, 1), 8), dtype=torch.float32, device=beam.z.device)
+    r = torch.zeros_like(u)
+    n = torch.zeros(1, dtype=torch.int64, device=beam.z.device)
+    _check(lib().trk_surrogate_pairs(s.handle, C.byref(beam.struct()), u.data_ptr(), r.data_ptr(),
+                                     n.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     _stream_handle(stream)))
+    return u, r, n
+
+
+def surrogate_fit_scale(s: Surrogate, r, n: int, ws, stream=None) -> np.ndarray:
+    _check(lib().trk_surrogate_fit_scale(s.handle, r.data_ptr(), int(n), ws.data_ptr(), ws.numel(),
+                                         _stream_handle(stream)))
+    return s.info()["D"]
+
+
+def surrogate_apply(s: Surrogate, m: Mlp, beam: Beam, ws, first_pass: int = 0,
+                    precision: int = MLP_BF16X2, n_admitted=None, stream=None) -> None:
+    _check(lib().trk_surrogate_apply(s.handle, m.handle, C.byref(beam.struct()), first_pass,
+                                     precision,
+                                     n_admitted.data_ptr() if n_admitted is not None else None,
+                                     ws.data_ptr(), ws.numel(), _stream_handle(stream)))

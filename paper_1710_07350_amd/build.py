@@ -26,9 +26,7 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["/opt/rocm/bin/hipcc", *FLAGS, *extra, "-o", tmp, *sources()]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,6 +37,24 @@ def build(verbose: bool = False, extra=()) -> str:
              if ln.strip() and "packed-fp32-ops" not in ln]
     if verbose and noise:
         print("\n".join(noise))
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every translation unit (in parallel) into _build/, then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        jobs.append((["/opt/rocm/bin/hipcc", *cflags, *extra, "-c", "-o", obj, src], obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    tmp = LIB + ".tmp"
+    _run(["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+          *[o for _, o in jobs]], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -8,16 +8,19 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "host.h"
 #include "trk_internal.h"
 
 using namespace trk;
 
-namespace {
+namespace trk {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -30,11 +33,6 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(TRK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                  \
-  do {                                       \
-    hipError_t e_ = (expr);                  \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
 
 // A pointer is accepted as "device" if the runtime knows it as device or
 // managed memory; plain host memory is rejected before any launch.
@@ -66,6 +64,32 @@ int check_beam(const trk_beam *b) {
   return TRK_OK;
 }
 
+int check_ws(void *ws, size_t bytes, int64_t n_total) {
+  const size_t need = workspace_bytes(n_total);
+  if (bytes < need) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", bytes, need);
+    return fail(TRK_ERANGE, buf);
+  }
+  return check_dev(ws, "workspace");
+}
+
+void beam_ptrs(const trk_beam *b, double *z[6]) {
+  z[0] = b->x;
+  z[1] = b->xp;
+  z[2] = b->y;
+  z[3] = b->yp;
+  z[4] = b->s;
+  z[5] = b->dp;
+}
+
+}  // namespace host
+}  // namespace trk
+
+using namespace trk::host;
+
+namespace {
+
 // ------------------------------------------------------------------ profiling
 struct Prof {
   std::mutex mu;
@@ -95,6 +119,18 @@ hipError_t profiled(int cls, hipStream_t st, F &&launch) {
   g_prof.ev[cls].push_back({a, b});
   return e;
 }
+
+}  // namespace
+
+namespace trk {
+namespace host {
+hipError_t profiled_call(int cls, hipStream_t st, const std::function<hipError_t()> &launch) {
+  return profiled(cls, st, launch);
+}
+}  // namespace host
+}  // namespace trk
+
+namespace {
 
 // ------------------------------------------------------------------ constants
 // Fourth-order symmetric composition (Yoshida 1990): kicks c, drifts d.
@@ -198,19 +234,6 @@ constexpr uint32_t M_ALL = 63;
 }  // namespace
 
 // ------------------------------------------------------------------ lattice
-struct trk_lattice {
-  std::vector<DevElem> rec;
-  std::vector<double> pool;
-  std::vector<trk_element> src;
-  std::vector<uint32_t> rd, wr;   // per element coordinate masks
-  std::vector<char> aper;         // element has an aperture
-  std::vector<int> vslot;         // -1 or ordinal among pass-varying elements
-  int nvar = 0;
-  bool has_wake = false;
-  int max_bins = 0;
-  DevElem *d_rec = nullptr;
-  double *d_pool = nullptr;
-};
 
 extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_lattice **out) {
   if (out == nullptr) return fail(TRK_EINVAL, "out is NULL");
@@ -477,25 +500,6 @@ extern "C" size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total) {
 }
 
 namespace {
-
-int check_ws(void *ws, size_t bytes, int64_t n_total) {
-  const size_t need = workspace_bytes(n_total);
-  if (bytes < need) {
-    char buf[128];
-    std::snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", bytes, need);
-    return fail(TRK_ERANGE, buf);
-  }
-  return check_dev(ws, "workspace");
-}
-
-void beam_ptrs(const trk_beam *b, double *z[6]) {
-  z[0] = b->x;
-  z[1] = b->xp;
-  z[2] = b->y;
-  z[3] = b->yp;
-  z[4] = b->s;
-  z[5] = b->dp;
-}
 
 int grid_stride_blocks(int64_t n_total) {
   const int64_t nb = nblocks(n_total);

@@ -195,6 +195,35 @@ def batch_variant_sizes(nvar: int = 256, seed: int = 0, lo: float = 1e3,
     return np.floor(lo * (hi / lo) ** u).astype(np.int64)
 
 
+# --------------------------------------------------------------------------
+# surrogate network: initial weights
+# --------------------------------------------------------------------------
+MLP_SHAPES = [("W1", (256, 6)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+              ("W3", (256, 256)), ("b3", (256,)), ("W4", (6, 256)), ("b4", (6,))]
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameter vector (FP32, layout W1, b1, ..., W4, b4 with
+    W[out][in]): weights uniform in +-1/sqrt(fan_in) (PCG64([seed, 5])),
+    biases zero; the s column of W1 and the delta row of W4 are zero and W4 is
+    scaled by 0.1."""
+    rng = np.random.Generator(np.random.PCG64([seed, 5]))
+    parts = []
+    for name, shp in MLP_SHAPES:
+        if name.startswith("W"):
+            lim = 1.0 / math.sqrt(shp[1])
+            a = rng.uniform(-lim, lim, size=shp).astype(np.float32)
+            if name == "W1":
+                a[:, 4] = 0.0
+            if name == "W4":
+                a[5, :] = 0.0
+                a *= np.float32(0.1)
+        else:
+            a = np.zeros(shp, dtype=np.float32)
+        parts.append(a.reshape(-1))
+    return np.concatenate(parts)
+
+
 def workload(name: str):
     """(lattice, beam kwargs, passes, p_ref) of a named workload."""
     if name == "fodo":

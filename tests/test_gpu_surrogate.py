@@ -1,0 +1,333 @@
+"""Learned section surrogate on the GPU against the surrogate oracle.
+
+Bit for bit: the section's linear map and gate constants (central
+differences of the bit-exact tracker, the same host arithmetic), the gate's
+decisions, the sampler's draws, the training pairs, the Adam update.  Within
+derived bounds: the network forward (FP32 accumulation of bfloat16 products
+against FP64), its gradient (bfloat16 backward operands), the residual scale.
+Plain-tracking fallback: bit for bit with the oracle tracker.  The gain test
+trains the network on the GPU and checks that it beats the linear map alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as S
+from paper_1710_07350_amd import binding as B
+from paper_1710_07350_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HW = 6.0 * np.array(inputs.BEAM_SIGMAS)
+APER = (10e-3, 5e-3)
+MARGIN = 0.5
+H_REL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def section():
+    return inputs.ring_lattice(seed=0)[:100]
+
+
+@pytest.fixture(scope="module")
+def ref():
+    """Oracle linear map, gate constants and sampler box of the section."""
+    sec = section()
+    C, R = S.linear_map(oracle, sec, HW, H_REL)
+    parts = [S.linear_map(oracle, sec[:k + 1], HW, H_REL)[1] for k in range(len(sec))]
+    g = S.gate_constants(R, parts, HW, MARGIN, *APER)
+    sw = S.sample_widths(g, *APER)
+    return dict(C=C, R=R, g=g, sw=sw)
+
+
+@pytest.fixture(scope="module")
+def surr(torch):
+    L = B.Lattice(section())
+    return B.Surrogate(L, HW, MARGIN, APER, H_REL)
+
+
+def random_params(seed):
+    p = S.init_params(seed)
+    P = S.unpack(p)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3"):
+        P[k][...] = rng.uniform(-0.3, 0.3, P[k].shape).astype(np.float32)
+    P["b4"][:5] = rng.uniform(-0.1, 0.1, 5).astype(np.float32)
+    return p
+
+
+def rows(torch, u):
+    a = np.zeros((u.shape[0], 8), dtype=np.float32)
+    a[:, :u.shape[1]] = u
+    return torch.from_numpy(a).cuda()
+
+
+# ------------------------------------------------------------------ network
+@pytest.mark.parametrize("n", [1, 63, 1000, 4096 + 17])
+def test_forward_bf16x2_matches_oracle(torch, n):
+    p = random_params(1)
+    m = B.Mlp(p)
+    u = np.random.default_rng(n).uniform(-1, 1, (n, 6)).astype(np.float32)
+    u[:, S.S_COORD] = 0.0
+    got = B.mlp_forward(m, rows(torch, u), B.MLP_BF16X2).cpu().numpy()
+    want = S.forward(p, u.astype(np.float64), "bf16x2")
+    exact = S.forward(p, u.astype(np.float64), "exact")
+    scale = np.abs(want).max()
+    err = np.abs(got[:, :6] - want).max()
+    print(f"n={n}: |gpu - oracle(bf16x2)| = {err:.3e} of scale {scale:.3e}; "
+          f"|gpu - exact| = {np.abs(got[:, :6] - exact).max():.3e}")
+    assert err <= 2e-4 * scale
+    assert (got[:, 6:] == 0).all()
+
+
+def test_forward_bf16_matches_oracle(torch):
+    p = random_params(2)
+    m = B.Mlp(p)
+    u = np.random.default_rng(3).uniform(-1, 1, (2048, 6)).astype(np.float32)
+    got = B.mlp_forward(m, rows(torch, u), B.MLP_BF16).cpu().numpy()[:, :6]
+    want = S.forward(p, u.astype(np.float64), "bf16")
+    scale = np.abs(want).max()
+    d = np.abs(got - want) / scale
+    print(f"bf16: median {np.median(d):.2e}, 99.9% {np.quantile(d, 0.999):.2e}, max {d.max():.2e}")
+    # an activation rounded on the other side of a bfloat16 tie (FP32 vs FP64
+    # accumulation) moves an output by about one bfloat16 unit of one term
+    assert np.quantile(d, 0.999) <= 1e-4 and d.max() <= 1e-2
+
+
+def test_forward_ignores_s_and_rejects_bad_precision(torch):
+    p = random_params(4)
+    m = B.Mlp(p)
+    u = np.random.default_rng(5).uniform(-1, 1, (256, 6)).astype(np.float32)
+    u2 = u.copy()
+    u2[:, S.S_COORD] = np.random.default_rng(6).uniform(-1, 1, 256)
+    a = B.mlp_forward(m, rows(torch, u), B.MLP_BF16X2).cpu().numpy()
+    b = B.mlp_forward(m, rows(torch, u2), B.MLP_BF16X2).cpu().numpy()
+    assert np.array_equal(a, b)
+    with pytest.raises(B.TrkError):
+        B.mlp_forward(m, rows(torch, u), 7)
+
+
+def test_gradient_matches_oracle(torch):
+    p = random_params(7)
+    m = B.Mlp(p)
+    n = 512
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32)
+    u[:, S.S_COORD] = 0.0
+    t = (rng.standard_normal((n, 6)) * 0.3).astype(np.float32)
+    t[:, S.D_COORD] = 0.0
+    ws = B.mlp_workspace(n)
+    g, loss = B.mlp_backward(m, rows(torch, u), rows(torch, t), ws, B.MLP_BF16X2)
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = S.loss_and_grad(p, u.astype(np.float64), t.astype(np.float64))
+    assert float(loss.item()) == pytest.approx(lref, rel=1e-4)
+    G, R = S.unpack(g), S.unpack(gref)
+    for k in G:
+        rel = np.linalg.norm(G[k] - R[k]) / np.linalg.norm(R[k])
+        cos = float((G[k] * R[k]).sum() / (np.linalg.norm(G[k]) * np.linalg.norm(R[k])))
+        print(f"{k}: rel L2 {rel:.2e}, cos {cos:.8f}")
+        # bfloat16 operands of the backward products carry 2^-9 relative error
+        assert rel <= 1e-2 and cos >= 0.9999, k
+    assert (G["W1"][:, S.S_COORD] == 0).all()
+
+
+def test_adam_step_bit_exact(torch):
+    p = random_params(9)
+    m = B.Mlp(p)
+    rng = np.random.default_rng(10)
+    w = p.copy()
+    mm = np.zeros_like(w)
+    vv = np.zeros_like(w)
+    for step, lr in ((1, 1e-3), (2, 5e-4), (3, 2e-3)):
+        g = (rng.standard_normal(S.N_PARAM) * 1e-2).astype(np.float32)
+        B.mlp_adam_step(m, torch.from_numpy(g).cuda(), lr)
+        w, mm, vv = S.adam(w, mm, vv, g, step, lr)
+        got = m.params()
+        assert np.array_equal(got.view(np.uint32), w.view(np.uint32)), step
+
+
+def test_training_fits_a_smooth_map(torch):
+    """Training on a smooth synthetic target lowers the loss by 10x."""
+    rng = np.random.default_rng(11)
+    n = 1 << 15
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32)
+    u[:, S.S_COORD] = 0.0
+    x = u.astype(np.float64)
+    t = np.zeros((n, 6))
+    t[:, 0] = x[:, 0] * x[:, 1] + 0.5 * x[:, 5] ** 2
+    t[:, 1] = np.sin(x[:, 0]) - x[:, 2] * x[:, 3]
+    t[:, 2] = x[:, 2] * x[:, 5]
+    t[:, 3] = x[:, 3] ** 2 - x[:, 1] * x[:, 5]
+    t[:, 4] = x[:, 0] ** 2 + x[:, 1] ** 2
+    m = B.Mlp(S.init_params(12))
+    ws = B.mlp_workspace(1024)
+    loss = B.mlp_train(m, rows(torch, u), rows(torch, t.astype(np.float32)), np.ones(6), ws,
+                       batch=1024, epochs=8, lr0=2e-3, lr_min=1e-4, seed=3).cpu().numpy()
+    print("epoch losses", loss)
+    assert np.isfinite(loss).all() and loss[-1] < 0.1 * loss[0]
+    # the trained master weights evaluated by the oracle reproduce the GPU forward
+    pw = m.params()
+    got = B.mlp_forward(m, rows(torch, u[:512]), B.MLP_BF16X2).cpu().numpy()[:, :6]
+    want = S.forward(pw, x[:512], "bf16x2")
+    assert np.abs(got - want).max() <= 2e-4 * np.abs(want).max()
+
+
+# ------------------------------------------------------------------ section
+def test_linear_map_and_gate_constants_bit_exact(surr, ref):
+    I = surr.info()
+    assert np.array_equal(I["C"], ref["C"]) and np.array_equal(I["R"], ref["R"])
+    g = ref["g"]
+    pairs = [("beta_x", "bx"), ("gamma_x", "gx"), ("eta", "eta"), ("etap", "etap"),
+             ("beta_y", "by"), ("gamma_y", "gy"), ("beta_hat_x", "bhx"),
+             ("beta_hat_y", "bhy"), ("eta_hat", "eh"), ("lim", "lim")]
+    for a, b in pairs:
+        assert I[a] == g[b], (a, I[a], g[b])
+    assert 2.0 * I["alpha_x"] == g["ax2"] and 2.0 * I["alpha_y"] == g["ay2"]
+    assert np.array_equal(I["sample_half_width"], ref["sw"])
+
+
+@pytest.mark.parametrize("n", [1, 255, 50001])
+def test_gate_bit_exact(torch, surr, ref, n):
+    d = inputs.uniform_box_beam(n, seed=30 + n, half_widths=ref["sw"] * 1.3)
+    beam = B.Beam.from_inputs(d)
+    got = B.surrogate_gate(surr, beam).cpu().numpy().astype(bool)
+    want = S.gate(d["z"], ref["g"])
+    assert np.array_equal(got, want)
+    if n > 1000:
+        assert 0 < want.sum() < n
+    # particles beyond n_alive are never admitted
+    beam.n_alive.fill_(n // 2)
+    got = B.surrogate_gate(surr, beam).cpu().numpy().astype(bool)
+    assert not got[n // 2:].any() and np.array_equal(got[:n // 2], want[:n // 2])
+
+
+@pytest.mark.parametrize("n,first", [(1, 0), (2000, 12345)])
+def test_sampler_bit_exact(torch, surr, ref, n, first):
+    beam = B.Beam(np.zeros((6, n)), np.zeros(n, np.uint32), np.zeros(n, np.int64))
+    ws = surr.workspace(n)
+    nxt = B.surrogate_sample(surr, 77, first, beam, ws)
+    h = beam.host()
+    z, c_end = S.sample(oracle, ref["g"], ref["sw"], 77, first, n)
+    assert np.array_equal(h["z"], z)
+    assert np.array_equal(h["id"], np.arange(n, dtype=np.uint32))
+    assert (h["lost_at"] == -1).all() and h["n_alive"] == n
+    assert first + 0 < c_end <= nxt and (nxt - first) % (1 << 22) == 0
+
+
+def test_pairs_bit_exact(torch, surr, ref):
+    n = 4000
+    d = inputs.uniform_box_beam(n, seed=41, half_widths=ref["sw"])
+    beam = B.Beam.from_inputs(d)
+    ws = surr.workspace(n)
+    u, r, npairs = B.surrogate_pairs(surr, beam, ws)
+    npairs = int(npairs.item())
+    adm = S.gate(d["z"], ref["g"])
+    zin = d["z"][:, adm]
+    ob = oracle.Beam(zin, np.arange(zin.shape[1], dtype=np.uint32),
+                     np.full(zin.shape[1], -1, np.int64))
+    oracle.track(ob, section(), 1)
+    assert (ob.lost_at < 0).all() and npairs == zin.shape[1] > 100
+    order = np.argsort(ob.id, kind="stable")
+    rr = S.residual(ref["C"], ref["R"], zin, ob.z[:, order])
+    uu = S.normalise(zin, HW).astype(np.float32)
+    assert np.array_equal(u.cpu().numpy()[:npairs, :6], uu)
+    assert np.array_equal(r.cpu().numpy()[:npairs, :6], rr)
+    # the input beam is untouched
+    assert np.array_equal(beam.host()["z"], d["z"])
+    D = B.surrogate_fit_scale(surr, r, npairs, ws)
+    Dref = np.sqrt((rr.astype(np.float64) ** 2).mean(axis=0))
+    np.testing.assert_allclose(D[:5], Dref[:5], rtol=1e-12)
+    assert D[5] == 0.0
+
+
+def test_apply_fallback_bit_exact_and_surrogate_within_bound(torch, surr, ref):
+    """Wide Gaussian beam: admitted particles get C + R z + D o (compared with
+    the oracle's evaluation of the same network), rejected ones are tracked
+    element by element (bit for bit with the oracle, losses included)."""
+    n = 6000
+    d = inputs.gaussian_beam(n, seed=51, sigmas=(2e-3, 2e-4, 1.5e-3, 1.5e-4, 1e-3, 1.5e-3))
+    p = random_params(13)
+    m = B.Mlp(p)
+    sw = surr.workspace(n)
+    # scale from a small pair set so that D is set
+    pd = inputs.uniform_box_beam(3000, seed=52, half_widths=ref["sw"])
+    pb = B.Beam.from_inputs(pd)
+    _, r, npairs = B.surrogate_pairs(surr, pb, sw)
+    D = B.surrogate_fit_scale(surr, r, int(npairs.item()), sw)
+    beam = B.Beam.from_inputs(d)
+    nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
+    B.surrogate_apply(surr, m, beam, sw, first_pass=3, n_admitted=nadm)
+    h = beam.host()
+    adm = S.gate(d["z"], ref["g"])
+    assert int(nadm.item()) == int(adm.sum()) and 0 < adm.sum() < n
+    # rejected: plain tracking
+    rej = ~adm
+    ob = oracle.Beam(d["z"][:, rej], d["id"][rej], d["lost_at"][rej])
+    oracle.track(ob, section(), 1, first_pass=3)
+    byid = {int(i): k for k, i in enumerate(h["id"])}
+    gi = np.array([byid[int(i)] for i in ob.id])
+    assert np.array_equal(h["z"][:, gi], ob.z) and np.array_equal(h["lost_at"][gi], ob.lost_at)
+    assert (ob.lost_at >= 0).any()
+    # admitted: the surrogate formula
+    ai = np.array([byid[int(i)] for i in d["id"][adm]])
+    want = S.apply(p, ref["C"], ref["R"], D, HW, d["z"][:, adm], "bf16x2")
+    got = h["z"][:, ai]
+    assert np.array_equal(got[S.D_COORD], d["z"][S.D_COORD, adm])
+    o_scale = np.abs(S.forward(p, S.normalise(d["z"][:, adm], HW), "bf16x2")).max()
+    for k in range(5):
+        assert np.abs(got[k] - want[k]).max() <= 2e-4 * o_scale * D[k] + 1e-18, k
+    assert (h["lost_at"][ai] == -1).all()
+    # compaction: alive first in id order, lost after
+    na = h["n_alive"]
+    assert (h["lost_at"][:na] == -1).all() and (h["lost_at"][na:] >= 0).all()
+    assert (np.diff(h["id"][:na].astype(np.int64)) > 0).all()
+
+
+def test_gain_over_linear_map(torch, surr, ref):
+    """The network trained on the GPU lowers both the RMS and the largest
+    error of the linear map alone, judged against the oracle tracker."""
+    n_train = 1 << 17
+    beam = B.Beam(np.zeros((6, n_train)), np.zeros(n_train, np.uint32), np.zeros(n_train, np.int64))
+    sw = surr.workspace(n_train)
+    B.surrogate_sample(surr, 5, 0, beam, sw)
+    u, r, npairs = B.surrogate_pairs(surr, beam, sw)
+    npairs = int(npairs.item())
+    D = B.surrogate_fit_scale(surr, r, npairs, sw)
+    inv = [1.0 / v if v > 0 else 0.0 for v in D]
+    m = B.Mlp(S.init_params(21))
+    mws = B.mlp_workspace(2048)
+    loss = B.mlp_train(m, u, r, inv, mws, batch=2048, epochs=40, lr0=2e-3, lr_min=2e-5,
+                       seed=9, n_pairs=npairs).cpu().numpy()
+    # fresh test points from another seed, tracked by the oracle
+    n_test = 1500
+    z, _ = S.sample(oracle, ref["g"], ref["sw"], 6, 0, n_test)
+    tb = B.Beam(z, np.arange(n_test, dtype=np.uint32), np.full(n_test, -1, np.int64))
+    ws2 = surr.workspace(n_test)
+    nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
+    B.surrogate_apply(surr, m, tb, ws2, n_admitted=nadm)
+    h = tb.host()
+    assert int(nadm.item()) == n_test
+    ob = oracle.Beam(z, np.arange(n_test, dtype=np.uint32), np.full(n_test, -1, np.int64))
+    oracle.track(ob, section(), 1)
+    assert (ob.lost_at < 0).all()
+    o1 = np.argsort(h["id"])
+    o2 = np.argsort(ob.id)
+    exact = ob.z[:, o2]
+    sur = h["z"][:, o1]
+    lin = S.linear_part(ref["C"], ref["R"], z)
+    e_lin = np.abs(lin[:5] - exact[:5])
+    e_sur = np.abs(sur[:5] - exact[:5])
+    print("loss", loss[[0, len(loss) // 2, -1]])
+    for k in range(5):
+        print(f"coord {k}: linear rms {np.sqrt((e_lin[k]**2).mean()):.3e} max {e_lin[k].max():.3e}"
+              f" | surrogate rms {np.sqrt((e_sur[k]**2).mean()):.3e} max {e_sur[k].max():.3e}")
+    for k in range(5):
+        assert np.sqrt((e_sur[k] ** 2).mean()) < 0.2 * np.sqrt((e_lin[k] ** 2).mean()), k
+        assert e_sur[k].max() < 0.5 * e_lin[k].max(), k
+    assert np.array_equal(sur[S.D_COORD], z[S.D_COORD])
