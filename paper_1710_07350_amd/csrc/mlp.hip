@@ -48,6 +48,16 @@ __device__ __forceinline__ float bf16_float(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
+// two floats to two bfloat16 (nearest even) packed low-first, one
+// v_cvt_pk_bf16_f32
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const bf16x2v v = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+  return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ float lo_half(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_half(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
 __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
@@ -180,6 +190,122 @@ __device__ void mlp_tile(const MlpDev &m, uint16_t *hh, uint16_t *hl, float *os,
   __syncthreads();
 }
 
+// ------------------------------------------------------------------ inference tile
+// Inference evaluates Y^T = W H^T: the weights are the A operand (rows =
+// output features, read from L2 one K step ahead of their use), the tile's
+// activations the B operand.  The accumulator of lane l then holds four
+// consecutive features 4(l/16).. of particle l%16, so the epilogue writes
+// each lane's four new activations with one 8-byte LDS store per half.  The
+// skip path reads the previous activation back as hi + lo (16 significant
+// bits) instead of keeping it in registers, which halves the register
+// footprint and lets two workgroups share a compute unit.
+template <int kX2, int K>
+__device__ __forceinline__ void mma_t(f32x4 (&acc)[4][4], const uint16_t *__restrict__ w, int wstride,
+                                      int f0, const uint16_t *bh, const uint16_t *bl, int bstride) {
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+  bf16x8 a[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) a[mt] = ld8(w + static_cast<size_t>(f0 + 16 * mt + r) * wstride + 8 * g);
+#pragma unroll 1
+  for (int kk = 0; kk < K / 32; ++kk) {
+    bf16x8 an[4];
+    if (kk + 1 < K / 32) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        an[mt] = ld8(w + static_cast<size_t>(f0 + 16 * mt + r) * wstride + 32 * (kk + 1) + 8 * g);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const bf16x8 b = ld8(bh + (16 * nt + r) * bstride + 32 * kk + 8 * g);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(acc[mt][nt], a[mt], b);
+      if constexpr (kX2) {
+        const bf16x8 b2 = ld8(bl + (16 * nt + r) * bstride + 32 * kk + 8 * g);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(acc[mt][nt], a[mt], b2);
+      }
+    }
+    if (kk + 1 < K / 32) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+    }
+  }
+}
+
+template <bool kFirst>
+__device__ __forceinline__ void epi_t(const f32x4 (&acc)[4][4], const float *__restrict__ bias,
+                                      uint16_t *hh, uint16_t *hl, int f0) {
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int f = f0 + 16 * mt + 4 * g;
+    float bb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bb[q] = bias[f + q];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int o = (16 * nt + r) * kLds + f;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = silu(acc[mt][nt][q] + bb[q]);
+      if constexpr (!kFirst) {
+        const uint2 oh = *reinterpret_cast<const uint2 *>(hh + o);
+        const uint2 ol = *reinterpret_cast<const uint2 *>(hl + o);
+        v[0] = (lo_half(oh.x) + lo_half(ol.x)) + v[0];
+        v[1] = (hi_half(oh.x) + hi_half(ol.x)) + v[1];
+        v[2] = (lo_half(oh.y) + lo_half(ol.y)) + v[2];
+        v[3] = (hi_half(oh.y) + hi_half(ol.y)) + v[3];
+      }
+      uint2 ph, pl;
+      ph.x = pack_bf16(v[0], v[1]);
+      ph.y = pack_bf16(v[2], v[3]);
+      pl.x = pack_bf16(v[0] - lo_half(ph.x), v[1] - hi_half(ph.x));
+      pl.y = pack_bf16(v[2] - lo_half(ph.y), v[3] - hi_half(ph.y));
+      *reinterpret_cast<uint2 *>(hh + o) = ph;
+      *reinterpret_cast<uint2 *>(hl + o) = pl;
+    }
+  }
+}
+
+// The network for one 64-particle tile whose inputs are in LDS (uh/ul,
+// aliased with hh/hl); leaves o[row][0..8) in os (columns >= 6 zero).
+template <int kX2>
+__device__ void infer_tile(const MlpDev &m, uint16_t *hh, uint16_t *hl, float *os) {
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4, w = threadIdx.x >> 6, f0 = 64 * w;
+  f32x4 acc[4][4];
+  zero(acc);
+  mma_t<kX2, kMlpInPad>(acc, m.w1f, kMlpInPad, f0, hh, hl, kULds);
+  __syncthreads();
+  epi_t<true>(acc, m.b1, hh, hl, f0);
+  __syncthreads();
+  zero(acc);
+  mma_t<kX2, kMlpHid>(acc, m.w2f, kMlpHid, f0, hh, hl, kLds);
+  __syncthreads();
+  epi_t<false>(acc, m.b2, hh, hl, f0);
+  __syncthreads();
+  zero(acc);
+  mma_t<kX2, kMlpHid>(acc, m.w3f, kMlpHid, f0, hh, hl, kLds);
+  __syncthreads();
+  epi_t<false>(acc, m.b3, hh, hl, f0);
+  __syncthreads();
+  // output layer: 16 output rows (6 used) x particles 16w..16w+15
+  f32x4 o{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int kk = 0; kk < kMlpHid / 32; ++kk) {
+    const bf16x8 a = ld8(m.w4f + r * kMlpHid + 32 * kk + 8 * g);
+    o = mma(o, a, ld8(hh + (16 * w + r) * kLds + 32 * kk + 8 * g));
+    if constexpr (kX2) o = mma(o, a, ld8(hl + (16 * w + r) * kLds + 32 * kk + 8 * g));
+  }
+  if (g < 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int out = 4 * g + q;
+      os[(16 * w + r) * 8 + out] = out < kMlpOut ? o[q] + m.b4[out] : 0.0f;
+    }
+  }
+  __syncthreads();
+}
+
 // input tile: 64 rows x 32 (6 used, s column zero) as hi/lo bf16
 __device__ __forceinline__ void put_input(uint16_t *uh, uint16_t *ul, int row, int k, float v) {
   const uint16_t hi = bf16_bits(v);
@@ -212,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward(const MlpDev m, const fl
     if (row0 + row < n && k != kMlpSCol) put_input(hh, hl, row, k, u[(row0 + row) * 8 + k]);
   }
   __syncthreads();
-  mlp_tile<kX2, false>(m, hh, hl, os, Save{});
+  infer_tile<kX2>(m, hh, hl, os);
   for (int i = threadIdx.x; i < kRows * 8; i += kBlock) {
     const int row = i / 8;
     if (row0 + row < n) out[row0 * 8 + i] = os[i];
@@ -247,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_surr_infer(const MlpDev m, const Sur
       if (k != kMlpSCol) put_input(hh, hl, threadIdx.x, k, static_cast<float>(z[k] * c.inv_hw[k]));
   }
   __syncthreads();
-  mlp_tile<kX2, false>(m, hh, hl, os, Save{});
+  infer_tile<kX2>(m, hh, hl, os);
   if (idx >= 0) {
 #pragma unroll
     for (int i = 0; i < kMlpDCol; ++i)
