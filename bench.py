@@ -39,6 +39,12 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/k_run_bunch_compressor_4e6_hbm_bytes.md); absent until measured
 # for the current kernel.
 TRAFFIC_PER_LAUNCH = {"bc": 99826187}
+# FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
+# particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
+# + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
+# run in which nobody is lost (profiles/k_run_fp64_flops.md)
+FP64_PEAK_TFLOPS = 78.6
+FP64_FLOP_PER_STEP = {"ring": 142.5, "fodo": 60.0}
 
 
 def parse():
@@ -54,6 +60,8 @@ def parse():
     ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--particles", type=float, default=None)
+    ap.add_argument("--sigma-scale", type=float, default=1.0,
+                    help="scale the Gaussian beam's sigmas (0.1: nobody is lost)")
     return ap.parse_args()
 
 
@@ -187,7 +195,7 @@ def surrogate_bench(args):
         work = src.clone()
         tws = B.Workspace(n)
         times = {"plain": [], "surr": []}
-        B.profile_enable(True)
+        B.profile_enable(True, classes=0b10)
         for rep in range(reps + 1):
             for mode in ("plain", "surr"):
                 work.copy_(src)
@@ -248,6 +256,48 @@ def surrogate_bench(args):
                   "fresh uniform points of the training domain (box ∩ gate)")
     box = one_set(inputs.uniform_box_beam(n, seed=61, half_widths=hw), "uniform +-6 sigma box")
     gauss = one_set(inputs.gaussian_beam(n, seed=62), "Gaussian ring beam")
+    # 100 ring turns of 1e6 particles: the section served by the surrogate for
+    # admitted particles each turn (the rest of the ring tracked plainly),
+    # against the whole ring tracked plainly; Philox kicks are keyed by
+    # (id, turn), so both runs see the same kicks.
+    nr, turns = 1_000_000, 100
+    ring = inputs.ring_lattice(seed=0)
+    Lring, Lrest = B.Lattice(ring), B.Lattice(ring[100:])
+    d0 = inputs.gaussian_beam(nr, seed=64)
+    plain, served = B.Beam.from_inputs(d0), B.Beam.from_inputs(d0)
+    wsr = B.Workspace(nr)
+    wss = sur.workspace(nr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(turns):
+        B.track(plain, Lring, 1, wsr, seed=7, first_pass=t)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
+    adm_sum = 0
+    t0 = time.perf_counter()
+    for t in range(turns):
+        B.surrogate_apply(sur, m, served, wss, first_pass=t, precision=prec, n_admitted=nadm)
+        B.track(served, Lrest, 1, wsr, seed=7, first_pass=t)
+        adm_sum += nadm
+    torch.cuda.synchronize()
+    t_served = time.perf_counter() - t0
+    hp, hs = plain.host(), served.host()
+    both = np.intersect1d(hp["id"][:hp["n_alive"]], hs["id"][:hs["n_alive"]])
+    pp = np.empty(nr, np.int64)
+    pp[hp["id"]] = np.arange(nr)
+    ps = np.empty(nr, np.int64)
+    ps[hs["id"]] = np.arange(nr)
+    drift = np.abs(hs["z"][:, ps[both]] - hp["z"][:, pp[both]])
+    ring100 = {"particles": nr, "turns": turns, "alive_plain": hp["n_alive"],
+               "alive_served": hs["n_alive"],
+               "admitted_per_turn": float(adm_sum.item()) / turns / nr,
+               "s_plain": round(t_plain, 3), "s_served": round(t_served, 3),
+               "max_drift": {k: float(drift[i].max()) for i, k in
+                             enumerate(["x", "xp", "y", "yp", "s", "dp"])},
+               "rms_drift": {k: float(np.sqrt((drift[i] ** 2).mean())) for i, k in
+                             enumerate(["x", "xp", "y", "yp", "s", "dp"])}}
+    print(json.dumps(ring100), file=sys.stderr, flush=True)
     flops = 2.0 * (6 * 256 + 2 * 256 * 256 + 256 * 6)
     ach = dom["admitted"] * flops / (dom["infer_ms"] / 1e3) / 1e12
     mx = dom["max_abs_error"]
@@ -264,6 +314,7 @@ def surrogate_bench(args):
            "error": {"max_m": max(mx["x"], mx["y"], mx["s"]), "max_rad": max(mx["xp"], mx["yp"]),
                      "meets_1e-6": max(mx.values()) <= 1e-6},
            "sets": [dom, box, gauss],
+           "ring_100_turns": ring100,
            "roofline": {"bound": "mfma", "kernel": "trk::k_surr_infer", "achieved": round(ach, 2),
                         "peak": 2500.0, "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4),
                         "traffic": None}}
@@ -398,6 +449,8 @@ def main():
         lat = inputs.ring_lattice(seed=0)
         n = int(args.particles or 1_000_000)
         beam_kw = dict(n=n, seed=0)
+        if args.sigma_scale != 1.0:
+            beam_kw["sigmas"] = tuple(args.sigma_scale * v for v in inputs.BEAM_SIGMAS)
         p_ref, passes_per_step = 1e9, 1
         steps = args.steps or 20
         warm = args.warmup if args.warmup is not None else 2
@@ -411,6 +464,8 @@ def main():
         lat = inputs.fodo_lattice()
         n = int(args.particles or (10_000 if wl == "fodo" else 10_000_000))
         beam_kw = dict(n=n, seed=0)
+        if args.sigma_scale != 1.0:
+            beam_kw["sigmas"] = tuple(args.sigma_scale * v for v in inputs.BEAM_SIGMAS)
         p_ref = 1e9
         passes_per_step = 10 if wl == "roof" else 100
         steps = args.steps or 5
@@ -511,6 +566,18 @@ def main():
             "traffic": TRAFFIC_PER_LAUNCH.get(wl),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
             "alg_bytes_per_launch": round(alg_bytes_per_launch)}
+    # a launch whose FP64 work per byte exceeds the machine balance is bound by
+    # the FP64 vector units: report it against their peak instead
+    fpp = FP64_FLOP_PER_STEP.get("fodo" if wl in ("fodo", "roof") else wl)
+    if fpp is not None:
+        steps_per_launch = total_steps / max(run_launches, 1)
+        flops = fpp * steps_per_launch
+        if flops / max(alg_bytes_per_launch, 1.0) > FP64_PEAK_TFLOPS / (HBM_PEAK_GBS / 1e3):
+            ach = flops / (avg_ms / 1e3) / 1e12
+            roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                         "traffic": None, "alg_flops_per_launch": flops,
+                         "fp64_flops_per_element_step": fpp})
 
     out = {"metric": "particle·element steps/s (FP64 tracking)", "value": value,
            "unit": "particle·element steps/s", "n_gpus": 1, "steps": steps,

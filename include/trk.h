@@ -256,7 +256,9 @@ int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes, int32_
 enum trk_mlp_precision { TRK_MLP_BF16 = 0, TRK_MLP_BF16X2 = 1 };
 
 typedef struct trk_mlp trk_mlp;
-/* copies params_host[TRK_MLP_NPARAM]; Adam moments zero, step count 0 */
+/* copies params_host[TRK_MLP_NPARAM]; Adam moments zero, step count 0.  The
+ * handle keeps the Adam step count on the host: calls that update it
+ * (trk_mlp_adam_step, trk_mlp_train) must not run from two threads at once. */
 int trk_mlp_create(const float *params_host, trk_mlp **out);
 void trk_mlp_destroy(trk_mlp *m);
 /* copies the master parameters to the host (synchronises the stream) */
@@ -392,7 +394,10 @@ const char *trk_status_string(int status);
 const char *trk_last_error(void);
 /* per-kernel-class device time (ms) and launch count accumulated with HIP
  * events while enabled; class 0 = fused element run, class 1 = surrogate
- * network inference. */
+ * network inference, class 2 = wake histogram, class 3 = wake convolution
+ * (inside trk_track).  trk_profile_enable: `on` is a bit mask of the classes
+ * to time (bit c = class c; 0 stops timing); a nonzero mask also clears the
+ * accumulated figures. */
 int trk_profile_enable(int32_t on);
 int trk_profile_read(int32_t kernel_class, double *total_ms, int64_t *launches);
 

@@ -377,8 +377,10 @@ def gauss(pid, step: int, tag: int, seed: int, stream=None):
     return out
 
 
-def profile_enable(on: bool) -> None:
-    _check(lib().trk_profile_enable(1 if on else 0))
+def profile_enable(on, classes: int = 1) -> None:
+    """Time launches with HIP events: `classes` is a bit mask (bit 0 fused
+    runs, 1 surrogate inference, 2 wake histogram, 3 wake convolution)."""
+    _check(lib().trk_profile_enable(int(classes) if on else 0))
 
 
 def profile_read(cls: int = 0):

@@ -93,7 +93,7 @@ namespace {
 // ------------------------------------------------------------------ profiling
 struct Prof {
   std::mutex mu;
-  bool on = false;
+  uint32_t mask = 0;  // bit c: class c is timed
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
   double ms[4] = {0, 0, 0, 0};
   int64_t launches[4] = {0, 0, 0, 0};
@@ -104,7 +104,7 @@ hipError_t profiled(int cls, hipStream_t st, F &&launch) {
   bool on;
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    on = g_prof.on;
+    on = ((g_prof.mask >> cls) & 1u) != 0;
   }
   if (!on) return launch();
   hipEvent_t a, b;
@@ -591,10 +591,20 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   }
 
   int prev_mm_n = 0;  // > 0: the previous launch left (min, max) partials
+  // Compaction is lazy: particles lost in a run keep their slots (the run
+  // kernel skips them by their loss record) until a histogram needs the
+  // alive set packed, or the call ends.  The final layout does not depend on
+  // when compaction runs.
+  bool dirty = false;
   for (size_t li = 0; li < plan.size(); ++li) {
     const Launch &L = plan[li];
     const bool starts_wake = lat->src[L.e0].kind == TRK_WAKE;
     if (starts_wake) {
+      if (dirty) {
+        HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
+                "compact");
+        dirty = false;
+      }
       const int nb = lat->src[L.e0].nbins;
       if (prev_mm_n == 0) {
         prev_mm_n = grid_stride_blocks(beam->n_total);
@@ -602,12 +612,18 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
                               TRK_MAX_BINS, st),
                 "minmax");
       }
-      HIP_TRY(launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part, prev_mm_n, nb,
-                               w.counts, w.range, st),
+      HIP_TRY(profiled(2, st,
+                       [&] {
+                         return launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part,
+                                                 prev_mm_n, nb, w.counts, w.range, st);
+                       }),
               "histogram");
-      HIP_TRY(launch_convolve(w.counts, nb, w.range, lat->src[L.e0].wake_tau0,
-                              lat->src[L.e0].wake_omega, opts->wake_mode, w.wake_v, w.wake_par,
-                              st),
+      HIP_TRY(profiled(3, st,
+                       [&] {
+                         return launch_convolve(w.counts, nb, w.range, lat->src[L.e0].wake_tau0,
+                                                lat->src[L.e0].wake_omega, opts->wake_mode,
+                                                w.wake_v, w.wake_par, st);
+                       }),
               "convolve");
     }
     // does the next launch start with a wake?
@@ -670,7 +686,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
     a.mom = lmom ? 1 : 0;
     a.mom_part = w.mom_part;
     a.mom_shift = w.mom_shift;
-    a.longit = opts->run_longit >= 0 && !lmom && !any_aper &&
+    a.chk_lost = dirty ? 1 : 0;
+    a.longit = opts->run_longit >= 0 && !lmom && !any_aper && !dirty &&
                ((a.ldmask | a.stmask) & ~(M_S | M_DP)) == 0 && (feat & ~(F_RF | F_WAKE)) == 0;
     const int grid = run_shape(a, beam->n_total, opts->run_ppt, opts->run_blocks);
     if (next_wake) {
@@ -685,10 +702,11 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
       HIP_TRY(launch_mom_finalize(w.mom_part, grid, L.npass, w.mom_shift, out, 28, nullptr, st),
               "moments");
     }
-    if (any_aper)
-      HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
-              "compact");
+    dirty = dirty || any_aper;
   }
+  if (dirty)
+    HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
+            "compact");
   return TRK_OK;
 }
 
@@ -1069,7 +1087,7 @@ extern "C" const char *trk_last_error(void) { return g_err.c_str(); }
 
 extern "C" int trk_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  g_prof.on = on != 0;
+  g_prof.mask = static_cast<uint32_t>(on) & 0xFu;
   if (on) {
     for (int c = 0; c < 4; ++c) {
       for (auto &p : g_prof.ev[c]) {

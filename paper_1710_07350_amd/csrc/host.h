@@ -19,7 +19,8 @@ int check_beam(const trk_beam *b);
 int check_ws(void *ws, size_t bytes, int64_t n_total);
 void beam_ptrs(const trk_beam *b, double *z[6]);
 // launch bracketed by HIP events while profiling is enabled (trk_profile_*);
-// classes: 0 fused element run, 1 surrogate network inference
+// classes: 0 fused element run, 1 surrogate network inference, 2 wake
+// histogram, 3 wake convolution
 hipError_t profiled_call(int cls, hipStream_t st, const std::function<hipError_t()> &launch);
 }  // namespace host
 }  // namespace trk

@@ -66,9 +66,14 @@ __device__ __forceinline__ f32x4 mma(f32x4 c, bf16x8 a, bf16x8 b) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float silu(float a) { return __fdividef(a, 1.0f + __expf(-a)); }
+// sigma(a) = 1 / (1 + 2^(-a log2 e)) with the hardware exp2 and reciprocal
+// (about 1 ulp each; a large negative a gives exp2 = inf and sigma = 0)
+__device__ __forceinline__ float sigmoid(float a) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a * -1.4426950408889634f));
+}
+__device__ __forceinline__ float silu(float a) { return a * sigmoid(a); }
 __device__ __forceinline__ float dsilu(float a) {
-  const float s = __fdividef(1.0f, 1.0f + __expf(-a));
+  const float s = sigmoid(a);
   return s * (1.0f + a * (1.0f - s));
 }
 

@@ -68,6 +68,10 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
 #pragma unroll
     for (int q = 0; q < kP; ++q) {
       act[q] = base + q * nthr < n;
+      if constexpr (!kLong) {
+        // a particle lost earlier in the same call still holds its slot
+        if (a.chk_lost && act[q]) act[q] = a.lost_at[base + q * nthr] < 0;
+      }
       alive[q] = act[q];
       rec[q] = -1;
     }

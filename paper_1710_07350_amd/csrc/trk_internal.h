@@ -75,6 +75,7 @@ struct RunArgs {
   uint32_t ldmask, stmask;  // bit k: coordinate k loaded / stored; bit 6: id
   uint32_t feat;            // element families present (selects the instantiation)
   int32_t longit;           // run reads/writes only s and delta, no apertures
+  int32_t chk_lost;         // slots below *n_alive may hold lost particles (lazy compaction)
   int32_t ppt;              // particles per thread (1, 2, 4, 8)
   int32_t grid_cap;         // grid-stride cap
   int64_t n_total;          // array length (bound of speculative loads)

@@ -47,3 +47,26 @@ def test_invalid_lattice_rejected_without_gpu():
     assert e.value.status == binding.TRK_EINVAL
     with pytest.raises(binding.TrkError):
         binding.Lattice([Element("MULT", k=1.0, order=0)])
+
+
+def test_surrogate_host_checks_without_gpu():
+    import ctypes as C
+    lib = binding.lib()
+    # sizes are pure host arithmetic
+    assert lib.trk_mlp_workspace_size(0) == 0
+    w1, w2 = lib.trk_mlp_workspace_size(64), lib.trk_mlp_workspace_size(8192)
+    assert 0 < w1 < w2
+    s1 = lib.trk_surrogate_workspace_size(None, 1000)
+    s2 = lib.trk_surrogate_workspace_size(None, 10_000_000)
+    assert 0 < s1 < s2 and s2 >= 100 * 10_000_000
+    # NULL handles and bad arguments are rejected before any device call
+    h = C.c_void_p()
+    assert lib.trk_mlp_create(None, C.byref(h)) == binding.TRK_EINVAL
+    assert lib.trk_surrogate_create(None, None, None, C.byref(h)) == binding.TRK_EINVAL
+    assert lib.trk_mlp_forward(None, None, 0, None, 0, None) == binding.TRK_EINVAL
+    o = binding.TrainOpts(64, 1, 0, 0, 1e-3, 1e-5, 0)
+    sc = (C.c_double * 6)(*([1.0] * 6))
+    assert lib.trk_mlp_train(None, None, None, 64, sc, C.byref(o), None, None, 0,
+                             None) == binding.TRK_EINVAL
+    info = binding.SurrInfo()
+    assert lib.trk_surrogate_get_info(None, C.byref(info)) == binding.TRK_EINVAL

@@ -127,6 +127,25 @@ def bc_bound_on_delta(d, lat, n0):
     return tot
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(max_elems_per_launch=1), dict(passes_per_launch=1)])
+def test_losses_before_a_wake(torch, kw):
+    """Apertures lose particles in runs that precede a wake within one call:
+    the lazily compacted beam must be packed before the histogram, and runs
+    after a lossy run skip the slots of the particles it lost."""
+    a = dict(aperture="RECT", ax=1.5e-3, ay=1.5e-3)
+    lat = [Element("EDRIFT", L=2.0, **a), Element("QUAD", L=0.2, k=1.2, **a),
+           Element("RFCA", volt=20e6, phase=math.radians(-20), freq=1.3e9),
+           Element("EDRIFT", L=1.0, **a),
+           Element("WAKE", wake_A=1e14, wake_tau0=10e-12, wake_omega=2 * math.pi * 50e9,
+                   charge=1e-9, nbins=256),
+           Element("MAP2", coef=inputs.chicane_coef())]
+    d = inputs.gaussian_beam(20_000, seed=8, sigmas=WIDE)
+    g = run_gpu(lat, d, 3, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, **kw)
+    r = run_oracle(lat, d, 3, p_ref=inputs.BC_P0_EV)
+    assert 0 < r["n_alive"] < 20_000
+    assert_bit_exact(g, r)
+
+
 @pytest.mark.parametrize("n", [100_000, 4_000_000])
 def test_bunch_compressor_fp64_bit_exact(torch, n):
     lat = inputs.bc_lattice()
