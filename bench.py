@@ -44,7 +44,7 @@ TRAFFIC_PER_LAUNCH = {"bc": 99826187}
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
 # run in which nobody is lost (profiles/k_run_fp64_flops.md)
 FP64_PEAK_TFLOPS = 78.6
-FP64_FLOP_PER_STEP = {"ring": 142.5, "fodo": 60.0}
+FP64_FLOP_PER_STEP = {"ring": 143.0, "fodo": 60.0}
 
 
 def parse():
