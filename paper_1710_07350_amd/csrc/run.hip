@@ -32,8 +32,8 @@ namespace trk {
 // the count's latency is not paid twice.  kLong: the run reads and writes
 // only s and delta (RF cavities, wake kicks, longitudinal maps), so only
 // those two coordinates are loaded and kept in registers.  The moments
-// variant uses kP = 1 and exactly one particle per thread (every thread
-// reaches the per-pass block reductions).
+// variant makes one pass over the grid with kP particles per thread, so
+// that every thread reaches the per-pass block reductions.
 template <uint32_t kFeat, bool kMom, int kP, bool kLong>
 __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
   const ConstElems elems = (ConstElems)a.elems;
@@ -84,11 +84,20 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
           apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
       }
       if constexpr (kMom) {
-        double d[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) d[k] = alive[0] ? z[0][k] - a.mom_shift[k] : 0.0;
         double *row = a.mom_part + (static_cast<int64_t>(p) * gridDim.x + blockIdx.x) * 28;
-        block_moment_row(alive[0] ? 1.0 : 0.0, d, row);
+        if constexpr (kP == 1) {
+          double d[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) d[k] = alive[0] ? z[0][k] - a.mom_shift[k] : 0.0;
+          block_moment_row(alive[0] ? 1.0 : 0.0, d, row);
+        } else {
+          double d[kP][6];
+#pragma unroll
+          for (int q = 0; q < kP; ++q)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) d[q][k] = alive[q] ? z[q][k] - a.mom_shift[k] : 0.0;
+          block_moment_row_multi<kP>(alive, d, row);
+        }
       }
     }
 #pragma unroll
@@ -135,7 +144,10 @@ void launch_ppt(const RunArgs &a, int grid, hipStream_t st) {
 template <uint32_t kFeat>
 void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
   if (a.mom) {
-    hipLaunchKernelGGL((k_run<kFeat, true, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.ppt >= 2)
+      hipLaunchKernelGGL((k_run<kFeat, true, 2, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_run<kFeat, true, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
   } else if constexpr (light(kFeat)) {
     if constexpr (longit_ok(kFeat)) {
       if (a.longit) {
@@ -156,8 +168,10 @@ void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
 int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req) {
   const int64_t nb = nblocks(n_total);
   if (a.mom) {
-    a.ppt = 1;
-    return static_cast<int>(nb < 1 ? 1 : nb);
+    // every thread reaches the per-pass block reductions: no grid stride
+    a.ppt = ppt_req >= 2 ? 2 : 1;
+    const int64_t g = (n_total + static_cast<int64_t>(kBlock) * a.ppt - 1) / (kBlock * a.ppt);
+    return static_cast<int>(g < 1 ? 1 : g);
   }
   int ppt = ppt_req > 0 ? ppt_req : (a.longit ? kLongPPT : (light(a.feat) ? kLightPPT : 1));
   if (!light(a.feat)) ppt = ppt >= 2 ? 2 : 1;

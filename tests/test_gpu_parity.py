@@ -77,10 +77,11 @@ def test_first_pass_offset_and_markers(torch):
 
 
 # ------------------------------------------------------------------ ring
-def test_ring_subset_parity(torch):
+@pytest.mark.parametrize("ppt", [0, 2])
+def test_ring_subset_parity(torch, ppt):
     lat = inputs.ring_lattice(seed=0)
     d = inputs.gaussian_beam(2000, seed=3, sigmas=(3e-3, 3e-4, 2e-3, 2e-4, 1e-3, 1e-3))
-    g = run_gpu(lat, d, 30, seed=77, moments=True)
+    g = run_gpu(lat, d, 30, seed=77, moments=True, run_ppt=ppt)
     r = run_oracle(lat, d, 30, seed=77, moments=True)
     assert 0 < r["n_alive"] < 2000
     assert_bit_exact(g, r)
