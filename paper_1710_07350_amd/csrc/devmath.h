@@ -84,8 +84,14 @@ __device__ __forceinline__ double own_cos(double x) {
 }
 
 // sin and cos of one argument from one reduction (the same values as own_sin
-// and own_cos)
+// and own_cos).  For |x| <= 0.78 < pi/4 the reduction is the identity
+// (k = rint(2x/pi) = 0, r = x exactly), so the kernels take x directly.
 __device__ __forceinline__ void own_sincos(double x, double &sn, double &cs) {
+  if (fabs(x) <= 0.78) {
+    sn = sin_kernel(x);
+    cs = cos_kernel(x);
+    return;
+  }
   int q;
   const double r = reduce_half_pi(x, q);
   const double sk = sin_kernel(r), ck = cos_kernel(r);

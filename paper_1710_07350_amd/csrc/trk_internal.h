@@ -15,7 +15,7 @@ constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
 constexpr int kLightPPT = 4;       // particles per thread of memory-bound runs
 constexpr int kLongPPT = 2;        // ... of runs that touch only s and delta
-constexpr int kLongRunGrid = 2048; // grid-stride cap of those runs (8 blocks per CU)
+constexpr int kLongRunGrid = 1024; // grid-stride cap of those runs (4 blocks per CU)
 constexpr int kMaxRunGrid = 4096;  // grid-stride cap of the run kernel
 
 // Device element kinds after host-side classification.  MAP2 maps are
