@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # 1 GiB copy gives), averaged over the runs of one pass
 # (profiles/k_run_bunch_compressor_4e6_hbm_bytes.md); absent until measured
 # for the current kernel.
-TRAFFIC_PER_LAUNCH = {"bc": 99826187}
+TRAFFIC_PER_LAUNCH = {"bc": 99795195}
 # FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
 # particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
