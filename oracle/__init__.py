@@ -20,7 +20,7 @@ from . import build as _build
 _LIB = None
 
 KIND = {"EDRIFT": 1, "QUAD": 2, "MAP2": 3, "MULT": 4, "KQUAD": 5, "CSBEND": 6,
-        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10}
+        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11}
 APER = {"NONE": 0, "RECT": 1, "ELLIPSE": 2}
 TAG_RAD = 2
 
@@ -64,6 +64,14 @@ def lib():
         L.orc_wake_table.argtypes = [d, d, i32, d, d, pd]
         L.orc_convolve.argtypes = [pu32, pd, i32, pd]
         L.orc_wake_kick.argtypes = [C.POINTER(OrcBeam), pd, pd, i32, d]
+        pi64 = C.POINTER(C.c_int64)
+        L.orc_dipole_quantum.restype = i64
+        L.orc_dipole_quantum.argtypes = [d]
+        L.orc_dipole_histogram.argtypes = [pd, pd, pd, pi64, i64, i32, pd, pu32, pi64, pi64]
+        L.orc_dipole_metres.argtypes = [pi64, i32, pd]
+        L.orc_trwake_table.argtypes = [d, d, i32, d, d, pd]
+        L.orc_convolve_f64.argtypes = [pd, pd, i32, pd]
+        L.orc_trwake_kick.argtypes = [C.POINTER(OrcBeam), pd, pd, pd, i32, d]
         L.orc_moments.argtypes = [C.POINTER(OrcBeam), pd]
         L.orc_compact.restype = i64
         L.orc_compact.argtypes = [C.POINTER(OrcBeam)]
@@ -199,6 +207,57 @@ def wake_kick(beam: Beam, rng, v, kfac: float) -> None:
     v = np.ascontiguousarray(v, dtype=np.float64)
     cb = beam.cstruct()
     lib().orc_wake_kick(C.byref(cb), _ptr(rng, C.c_double), _ptr(v, C.c_double), len(v), kfac)
+
+
+# ---------------------------------------------------------------- transverse wake
+def dipole_quantum(x: float) -> int:
+    """x as an integer multiple of 2^-40 m (clamped to 1 m, ties to even)."""
+    return int(lib().orc_dipole_quantum(x))
+
+
+def dipole_histogram(s, x, y, lost_at, nbins: int):
+    """(range, counts, dx, dy): the histogram of s and the per-bin sums of
+    the quantised x and y (int64, units of 2^-40 m)."""
+    s, x, y = (np.ascontiguousarray(a, dtype=np.float64) for a in (s, x, y))
+    la = np.ascontiguousarray(lost_at, dtype=np.int64)
+    rng = np.zeros(2)
+    cnt = np.zeros(nbins, dtype=np.uint32)
+    dx = np.zeros(nbins, dtype=np.int64)
+    dy = np.zeros(nbins, dtype=np.int64)
+    lib().orc_dipole_histogram(_ptr(s, C.c_double), _ptr(x, C.c_double), _ptr(y, C.c_double),
+                               _ptr(la, C.c_int64), len(s), nbins, _ptr(rng, C.c_double),
+                               _ptr(cnt, C.c_uint32), _ptr(dx, C.c_int64), _ptr(dy, C.c_int64))
+    return rng, cnt, dx, dy
+
+
+def dipole_metres(d) -> np.ndarray:
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    out = np.zeros(len(d))
+    lib().orc_dipole_metres(_ptr(d, C.c_int64), len(d), _ptr(out, C.c_double))
+    return out
+
+
+def trwake_table(smin: float, smax: float, nbins: int, tau0: float, omega: float):
+    w = np.zeros(nbins)
+    lib().orc_trwake_table(smin, smax, nbins, tau0, omega, _ptr(w, C.c_double))
+    return w
+
+
+def convolve_f64(c, w):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    v = np.zeros(len(w))
+    lib().orc_convolve_f64(_ptr(c, C.c_double), _ptr(w, C.c_double), len(w), _ptr(v, C.c_double))
+    return v
+
+
+def trwake_kick(beam: Beam, rng, vx, vy, kfac: float) -> None:
+    rng = np.ascontiguousarray(rng, dtype=np.float64)
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    cb = beam.cstruct()
+    lib().orc_trwake_kick(C.byref(cb), _ptr(rng, C.c_double), _ptr(vx, C.c_double),
+                          _ptr(vy, C.c_double), len(vx), kfac)
 
 
 def moments(beam: Beam) -> np.ndarray:

@@ -573,6 +573,97 @@ void orc_wake_kick(orc_beam *b, const double range[2], const double *v, int32_t 
   }
 }
 
+/* ======================================================================
+ * Transverse wake (the TRWAKE element of the element table; the transverse
+ * part of RFCW)
+ * ====================================================================== */
+
+/* A coordinate as an integer multiple of 2^-40 m: clamped to [-1, 1] m,
+ * rounded to the nearest multiple (ties to even); a NaN counts as 0. */
+int64_t orc_dipole_quantum(double x) {
+  if (x != x) return 0;
+  if (x > 1.0) x = 1.0;
+  if (x < -1.0) x = -1.0;
+  return (int64_t)nearbyint(x * 0x1p40);
+}
+
+/* The histogram of s (same range, bins and counts as orc_histogram) and, per
+ * bin, the sums of the quantised x and y of its particles, added as 64-bit
+ * two's-complement integers (modulo 2^64): exact, whatever the order. */
+void orc_dipole_histogram(const double *s, const double *x, const double *y,
+                          const int64_t *lost_at, int64_t n, int32_t nbins, double range[2],
+                          uint32_t *counts, int64_t *dx, int64_t *dy) {
+  orc_histogram(s, lost_at, n, nbins, range, counts);
+  for (int32_t b = 0; b < nbins; ++b) {
+    dx[b] = 0;
+    dy[b] = 0;
+  }
+  double width = range[1] - range[0];
+  double inv = width > 0.0 ? (double)nbins / width : 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (lost_at[i] >= 0) continue;
+    double f = (s[i] - range[0]) * inv;
+    if (!(f >= 0.0)) continue;
+    int64_t b = (int64_t)floor(f);
+    if (b > nbins - 1) b = nbins - 1;
+    dx[b] = (int64_t)((uint64_t)dx[b] + (uint64_t)orc_dipole_quantum(x[i]));
+    dy[b] = (int64_t)((uint64_t)dy[b] + (uint64_t)orc_dipole_quantum(y[i]));
+  }
+}
+
+/* dipole sums in metres: one rounding of the integer, then an exact scaling */
+void orc_dipole_metres(const int64_t *d, int32_t nbins, double *out) {
+  for (int32_t b = 0; b < nbins; ++b) out[b] = (double)d[b] * 0x1p-40;
+}
+
+/* Normalised transverse resonator wake W(tau)/A = exp(-tau/tau0) sin(omega
+ * tau) on the bin lags tau = m (smax - smin)/(nbins c); zero at m = 0. */
+void orc_trwake_table(double smin, double smax, int32_t nbins, double tau0, double omega,
+                      double *w) {
+  double width = smax - smin;
+  double delta = width > 0.0 ? width / (double)nbins : 0.0;
+  double dt = delta / C_LIGHT;
+  w[0] = 0.0;
+  for (int32_t m = 1; m < nbins; ++m) {
+    double t = (double)m * dt;
+    w[m] = orc_exp(-(t / tau0)) * orc_sin(omega * t);
+  }
+}
+
+/* causal convolution of binary64 weights, V[i] = sum_{j<=i} c_j W[i-j], j ascending */
+void orc_convolve_f64(const double *c, const double *w, int32_t nbins, double *v) {
+  for (int32_t i = 0; i < nbins; ++i) {
+    double acc = 0.0;
+    for (int32_t j = 0; j <= i; ++j) acc = fma(c[j], w[i - j], acc);
+    v[i] = acc;
+  }
+}
+
+/* transverse kick: the canonical momenta gain kfac V_x(s), kfac V_y(s), with
+ * V interpolated as for the energy kick; slopes are converted to canonical
+ * momenta and back as in the thin multipole */
+void orc_trwake_kick(orc_beam *b, const double range[2], const double *vx, const double *vy,
+                     int32_t nbins, double kfac) {
+  double width = range[1] - range[0];
+  double inv = width > 0.0 ? (double)nbins / width : 0.0;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < b->n; ++i) {
+    if (b->lost_at[i] >= 0) continue;
+    double z[6];
+    for (int k = 0; k < 6; ++k) z[k] = b->z[k][i];
+    double ux = interp_v(z[4], range[0], inv, vx, nbins);
+    double uy = interp_v(z[4], range[0], inv, vy, nbins);
+    double opd = 1.0 + z[5];
+    double px, py;
+    to_canonical(z, opd, &px, &py);
+    px = fma(kfac, ux, px);
+    py = fma(kfac, uy, py);
+    to_slopes(z, opd * opd, px, py);
+    b->z[1][i] = z[1];
+    b->z[3][i] = z[3];
+  }
+}
+
 /* Neumaier-compensated sum of an array */
 static double csum(const double *a, int64_t n) {
   double s = 0.0, c = 0.0;
@@ -687,6 +778,28 @@ int64_t orc_track(orc_beam *b, const orc_elem *lat, int32_t nelem, int32_t passe
         double kfac = ((el->charge / (double)b->n0) * el->wake_A) / P;
         orc_wake_kick(b, range, v, nb, kfac);
         free(counts);
+        free(w);
+        free(v);
+      }
+      if (el->kind == ORC_TRWAKE) {
+        int32_t nb = el->nbins;
+        uint32_t *counts = (uint32_t *)malloc((size_t)nb * sizeof(uint32_t));
+        int64_t *dq = (int64_t *)malloc((size_t)nb * 2 * sizeof(int64_t));
+        double *dm = (double *)malloc((size_t)nb * 2 * sizeof(double));
+        double *w = (double *)malloc((size_t)nb * sizeof(double));
+        double *v = (double *)malloc((size_t)nb * 2 * sizeof(double));
+        double range[2];
+        orc_dipole_histogram(b->z[4], b->z[0], b->z[2], b->lost_at, n, nb, range, counts, dq,
+                             dq + nb);
+        orc_dipole_metres(dq, 2 * nb, dm);
+        orc_trwake_table(range[0], range[1], nb, el->wake_tau0, el->wake_omega, w);
+        orc_convolve_f64(dm, w, nb, v);
+        orc_convolve_f64(dm + nb, w, nb, v + nb);
+        double kfac = ((el->charge / (double)b->n0) * el->wake_A) / P;
+        orc_trwake_kick(b, range, v, v + nb, nb, kfac);
+        free(counts);
+        free(dq);
+        free(dm);
         free(w);
         free(v);
       }

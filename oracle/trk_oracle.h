@@ -21,7 +21,8 @@ extern "C" {
 
 enum {
   ORC_EDRIFT = 1, ORC_QUAD = 2, ORC_MAP2 = 3, ORC_MULT = 4, ORC_KQUAD = 5,
-  ORC_CSBEND = 6, ORC_RFCA = 7, ORC_WAKE = 8, ORC_RADKICK = 9, ORC_MARKER = 10
+  ORC_CSBEND = 6, ORC_RFCA = 7, ORC_WAKE = 8, ORC_RADKICK = 9, ORC_MARKER = 10,
+  ORC_TRWAKE = 11
 };
 enum { ORC_APER_NONE = 0, ORC_APER_RECT = 1, ORC_APER_ELLIPSE = 2 };
 enum { ORC_TAG_RAD = 2 };
@@ -72,6 +73,19 @@ void orc_wake_table(double smin, double smax, int32_t nbins, double tau0, double
 void orc_convolve(const uint32_t *counts, const double *w, int32_t nbins, double *v);
 void orc_wake_kick(orc_beam *b, const double range[2], const double *v, int32_t nbins,
                    double kfac);
+/* transverse wake: dipole sums of x and y per bin in units of 2^-40 m
+ * (exact 64-bit integers), the sine resonator table, the binary64
+ * convolution and the kick of the canonical transverse momenta */
+int64_t orc_dipole_quantum(double x);
+void orc_dipole_histogram(const double *s, const double *x, const double *y,
+                          const int64_t *lost_at, int64_t n, int32_t nbins, double range[2],
+                          uint32_t *counts, int64_t *dx, int64_t *dy);
+void orc_dipole_metres(const int64_t *d, int32_t nbins, double *out);
+void orc_trwake_table(double smin, double smax, int32_t nbins, double tau0, double omega,
+                      double *w);
+void orc_convolve_f64(const double *c, const double *w, int32_t nbins, double *v);
+void orc_trwake_kick(orc_beam *b, const double range[2], const double *vx, const double *vy,
+                     int32_t nbins, double kfac);
 void orc_moments(const orc_beam *b, double out[28]);
 int64_t orc_compact(orc_beam *b);
 

@@ -28,10 +28,10 @@ import numpy as np
 
 # Element kinds (names follow the beamline element names of the paper's
 # element table: EDRIFT, QUAD matrix, thin multipole, KQUAD, CSBEND, RFCA,
-# WAKE; MAP2 is an explicit second-order transport map, RADKICK the random
-# energy kick).
+# WAKE, TRWAKE; MAP2 is an explicit second-order transport map, RADKICK the
+# random energy kick).
 KINDS = ("EDRIFT", "QUAD", "MAP2", "MULT", "KQUAD", "CSBEND", "RFCA", "WAKE",
-         "RADKICK", "MARKER")
+         "RADKICK", "MARKER", "TRWAKE")
 APERTURES = ("NONE", "RECT", "ELLIPSE")
 
 C_LIGHT = 299792458.0
@@ -48,11 +48,11 @@ class Element:
     volt: float = 0.0         # RF voltage [V]
     phase: float = 0.0        # RF phase [rad], cosine convention, crest at 0
     freq: float = 0.0         # RF frequency [Hz]
-    wake_A: float = 0.0       # resonator wake amplitude [V/C]
+    wake_A: float = 0.0       # resonator wake amplitude [V/C] (TRWAKE: [V/(C m)])
     wake_tau0: float = 0.0    # decay time [s]
     wake_omega: float = 0.0   # angular frequency [rad/s]
     charge: float = 0.0       # bunch charge [C]
-    nbins: int = 0            # histogram bins (WAKE)
+    nbins: int = 0            # histogram bins (WAKE, TRWAKE)
     sigma: float = 0.0        # RADKICK rms energy kick
     coef: Optional[np.ndarray] = None  # MAP2: 168 doubles C[6], R[6][6], T[6][21]
     aperture: str = "NONE"
@@ -149,6 +149,23 @@ def bc_lattice(ncav: int = 8, volt: float = 20e6, phase_deg: float = -20.0,
         out.append(Element("WAKE", wake_A=1e14, wake_tau0=10e-12,
                            wake_omega=2.0 * math.pi * 50e9, charge=1e-9,
                            nbins=nbins))
+    out.append(Element("MAP2", coef=chicane_coef()))
+    return out
+
+
+def rfcw_lattice(ncav: int = 8, volt: float = 20e6, phase_deg: float = -20.0,
+                 freq: float = 1.3e9, nbins: int = 1024, trans_A: float = 1e16) -> List[Element]:
+    """The bunch compressor with the transverse wake of each cavity: 8 x
+    [RFCA, WAKE, TRWAKE] then the chicane (the RF-cavity-with-wakes element
+    of the paper's element table, split into its parts)."""
+    phase = math.radians(phase_deg)
+    out: List[Element] = []
+    for _ in range(ncav):
+        out.append(Element("RFCA", volt=volt, phase=phase, freq=freq))
+        out.append(Element("WAKE", wake_A=1e14, wake_tau0=10e-12,
+                           wake_omega=2.0 * math.pi * 50e9, charge=1e-9, nbins=nbins))
+        out.append(Element("TRWAKE", wake_A=trans_A, wake_tau0=10e-12,
+                           wake_omega=2.0 * math.pi * 50e9, charge=1e-9, nbins=nbins))
     out.append(Element("MAP2", coef=chicane_coef()))
     return out
 
