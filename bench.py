@@ -33,12 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (FETCH_SIZE scaled by 2.000, WRITE_SIZE by 1.000, the factors a
-# 1 GiB copy gives), averaged over the runs of one pass
-# (profiles/k_run_bunch_compressor_4e6_hbm_bytes.md); absent until measured
-# for the current kernel.
-TRAFFIC_PER_LAUNCH = {"bc": 99795195}
+# HBM bytes of the dominant kernel per launch, keyed by (workload, element
+# limit per launch), from rocprofv3 FETCH_SIZE and WRITE_SIZE (FETCH_SIZE
+# scaled by 2.000, WRITE_SIZE by 1.000, the factors a 1 GiB copy gives),
+# averaged over the runs of one pass (profiles/*_hbm_bytes.md); absent until
+# measured for the current kernel.
+TRAFFIC_PER_LAUNCH = {("bc", 0): 99795195, ("roof", 1): 734042624}
 # FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
 # particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
@@ -563,7 +563,7 @@ def main():
     roof = {"bound": "hbm", "kernel": "trk::k_run (fused element run)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC_PER_LAUNCH.get(wl),
+            "traffic": TRAFFIC_PER_LAUNCH.get((wl, args.fusion)),
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
             "alg_bytes_per_launch": round(alg_bytes_per_launch)}
     # a launch whose FP64 work per byte exceeds the machine balance is bound by

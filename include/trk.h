@@ -65,6 +65,11 @@ extern "C" {
  *   TRK_WAKE    longitudinal wake: histogram of s into nbins bins, causal
  *               convolution with W(t) = A exp(-t/tau0) cos(omega t), energy
  *               kick; charge = bunch charge [C] (Sec. 2.2-2.3).
+ *   TRK_TRWAKE  transverse wake (the transverse part of the RF cavity with
+ *               wakes in the element table): the histogram of s with, per
+ *               bin, the sums of x and y; their causal convolution with
+ *               W(t) = A exp(-t/tau0) sin(omega t), A in V/(C m); a kick of
+ *               the canonical transverse momenta (see trk_trwake_kick).
  *   TRK_RADKICK random energy kick delta += sigma g, g ~ N(0,1) from
  *               Philox4x32-10 with counter (id, pass, 2, 0), key = seed.
  *   TRK_MARKER  nothing (carries an aperture only).
@@ -74,7 +79,8 @@ extern "C" {
  * A non-finite x or y fails every aperture. */
 enum trk_kind {
   TRK_EDRIFT = 1, TRK_QUAD = 2, TRK_MAP2 = 3, TRK_MULT = 4, TRK_KQUAD = 5,
-  TRK_CSBEND = 6, TRK_RFCA = 7, TRK_WAKE = 8, TRK_RADKICK = 9, TRK_MARKER = 10
+  TRK_CSBEND = 6, TRK_RFCA = 7, TRK_WAKE = 8, TRK_RADKICK = 9, TRK_MARKER = 10,
+  TRK_TRWAKE = 11
 };
 enum trk_aperture { TRK_APER_NONE = 0, TRK_APER_RECT = 1, TRK_APER_ELLIPSE = 2 };
 enum trk_wake_mode { TRK_WAKE_FP64 = 0, TRK_WAKE_FP32_MFMA = 1 };
@@ -84,7 +90,7 @@ typedef struct trk_element {
   int32_t aperture;  /* enum trk_aperture */
   int32_t order;     /* TRK_MULT order, 1..8 */
   int32_t nsteps;    /* TRK_KQUAD/TRK_CSBEND integration steps, >= 1 */
-  int32_t nbins;     /* TRK_WAKE bins, 2..TRK_MAX_BINS */
+  int32_t nbins;     /* TRK_WAKE bins, 2..TRK_MAX_BINS; TRK_TRWAKE 2..TRK_MAX_TRBINS */
   int32_t reserved;
   double L, k, angle;
   double volt, phase, freq;
@@ -95,6 +101,7 @@ typedef struct trk_element {
 } trk_element;
 
 #define TRK_MAX_BINS 4096
+#define TRK_MAX_TRBINS 2048 /* bins of a TRK_TRWAKE */
 #define TRK_MAX_ELEMENTS 65536
 
 /* ------------------------------------------------------------------ beam */
@@ -128,7 +135,10 @@ typedef struct trk_opts {
   int32_t run_blocks;           /* grid cap of grid-stride runs (0 = automatic) */
   int32_t run_longit;           /* runs touching only s and delta: 0 automatic
                                    (two-coordinate kernel), -1 generic kernel */
-  int32_t reserved;
+  int32_t run_nt;               /* memory-bound runs: 1 non-temporal coordinate
+                                   loads and stores, -1 cached, 0 automatic
+                                   (non-temporal when the coordinates the run
+                                   touches exceed 256 MB) */
   double p_ref_eV;              /* reference momentum at the entry of the first
                                    pass [eV/c]; raised by V cos(phase) per RFCA */
   double *moments;              /* NULL or device [passes][28]: per pass, after its
@@ -144,7 +154,7 @@ size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total);
 
 /* track(beam, lattice, passes): `passes` passes through the lattice.  Runs of
  * consecutive elements are fused into one kernel (coordinates loaded once,
- * kept in registers, stored once); TRK_WAKE splits runs.  Results do not
+ * kept in registers, stored once); TRK_WAKE and TRK_TRWAKE split runs.  Results do not
  * depend on the fusion depth.  Returns after enqueuing; the beam is
  * reordered (alive set first) when the last kernel completes. */
 int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes, const trk_opts *opts,
@@ -174,6 +184,35 @@ typedef struct trk_wake {
 int trk_wake_kick(trk_beam *beam, const uint32_t *counts_dev, int32_t nbins,
                   const double *range_dev, const trk_wake *w, double p_ref_eV, int32_t mode,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* dipole histogram (the histogram of Sec. 2.2 weighted by the transverse
+ * offsets): range_dev and counts_dev as trk_histogram; dipole_dev[2][nbins]
+ * (int64) = per bin, the sums over its alive particles of x (row 0) and y
+ * (row 1) in units of 2^-40 m, each coordinate first clamped to [-1, 1] m
+ * and rounded to the nearest unit (ties to even; NaN counts 0), the sums
+ * taken modulo 2^64 -- exact and independent of the summation order while
+ * a bin's true sum stays below 2^23 m.  2 <= nbins <= TRK_MAX_TRBINS. */
+int trk_dipole_histogram(const trk_beam *beam, int32_t nbins, double *range_dev,
+                         uint32_t *counts_dev, int64_t *dipole_dev, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* transverse wake convolution: v_dev[2][nbins] = per plane, V[i] =
+ * sum_{j<=i} D_j Wt[i-j] with D_j = dipole[j] 2^-40 (binary64),
+ * Wt[m] = exp(-t/tau0) sin(omega t), t = m (smax - smin)/(nbins c)
+ * (Wt[0] = 0).  TRK_WAKE_FP64: one fma chain per output, j ascending
+ * (bit-exact); TRK_WAKE_FP32_MFMA: D and Wt rounded once to binary32,
+ * products on FP32 matrix cores. */
+int trk_trwake_convolve(const int64_t *dipole_dev, int32_t nbins, const double *range_dev,
+                        double tau0, double omega, int32_t mode, double *v_dev, void *stream);
+
+/* transverse wake kick: the convolution above, then on alive particles the
+ * canonical momenta px = (1+delta) x'/sqrt(1+x'^2+y'^2) (and py) gain
+ * kfac V_x(s) and kfac V_y(s), kfac = ((charge/N0) A)/p_ref_eV, V
+ * interpolated as in trk_wake_kick; slopes are recomputed from the
+ * momenta.  Only x' and y' change. */
+int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
+                    const double *range_dev, const trk_wake *w, double p_ref_eV, int32_t mode,
+                    void *workspace, size_t workspace_bytes, void *stream);
 
 /* moments (Sec. 2.4 reductions): out_dev[28] = n, mean[6], central second
  * moments [21] (population normalisation) over alive particles, two passes,

@@ -17,14 +17,15 @@ LIB_PATH = os.path.join(HERE, "libtrk.so")
 
 TRK_OK, TRK_EINVAL, TRK_EPTR, TRK_EHIP, TRK_ENOMEM, TRK_ERANGE = 0, -1, -2, -3, -4, -5
 KIND = {"EDRIFT": 1, "QUAD": 2, "MAP2": 3, "MULT": 4, "KQUAD": 5, "CSBEND": 6,
-        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10}
+        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11}
 APER = {"NONE": 0, "RECT": 1, "ELLIPSE": 2}
 WAKE_FP64, WAKE_FP32_MFMA = 0, 1
 MAX_BINS = 4096
 
 # symbols declared in include/trk.h
 EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
-           "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_moments",
+           "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_dipole_histogram",
+           "trk_trwake_convolve", "trk_trwake_kick", "trk_moments",
            "trk_compact_lost", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
            "trk_batch_create", "trk_batch_destroy", "trk_batch_workspace_size",
@@ -64,7 +65,7 @@ class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first_pass", C.c_int32),
                 ("passes_per_launch", C.c_int32), ("max_elems_per_launch", C.c_int32),
                 ("wake_mode", C.c_int32), ("run_ppt", C.c_int32), ("run_blocks", C.c_int32),
-                ("run_longit", C.c_int32), ("reserved", C.c_int32),
+                ("run_longit", C.c_int32), ("run_nt", C.c_int32),
                 ("p_ref_eV", C.c_double), ("moments", C.c_void_p)]
 
 
@@ -119,6 +120,10 @@ def lib():
         L.trk_track.argtypes = [C.POINTER(BeamStruct), vp, i32, C.POINTER(Opts), vp, sz, vp]
         L.trk_histogram.argtypes = [C.POINTER(BeamStruct), i32, vp, vp, vp, sz, vp]
         L.trk_wake_convolve.argtypes = [vp, i32, vp, d, d, i32, vp, vp]
+        L.trk_dipole_histogram.argtypes = [C.POINTER(BeamStruct), i32, vp, vp, vp, vp, sz, vp]
+        L.trk_trwake_convolve.argtypes = [vp, i32, vp, d, d, i32, vp, vp]
+        L.trk_trwake_kick.argtypes = [C.POINTER(BeamStruct), vp, i32, vp, C.POINTER(Wake), d,
+                                      i32, vp, sz, vp]
         L.trk_wake_kick.argtypes = [C.POINTER(BeamStruct), vp, i32, vp, C.POINTER(Wake), d, i32,
                                     vp, sz, vp]
         L.trk_moments.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
@@ -299,11 +304,12 @@ class Workspace:
 def track(beam: Beam, lattice: Lattice, passes: int, ws: Workspace, seed: int = 0,
           first_pass: int = 0, p_ref: float = 1e9, moments=None, wake_mode: int = WAKE_FP64,
           passes_per_launch: int = 0, max_elems_per_launch: int = 0, run_ppt: int = 0,
-          run_blocks: int = 0, run_longit: int = 0, stream=None) -> None:
+          run_blocks: int = 0, run_longit: int = 0, run_nt: int = 0, stream=None) -> None:
     o = Opts()
     o.run_ppt = run_ppt
     o.run_blocks = run_blocks
     o.run_longit = run_longit
+    o.run_nt = run_nt
     o.seed = seed
     o.first_pass = first_pass
     o.passes_per_launch = passes_per_launch
@@ -337,6 +343,35 @@ def wake_kick(beam: Beam, counts, nbins: int, rng, A: float, tau0: float, omega:
     w = Wake(A, tau0, omega, charge)
     _check(lib().trk_wake_kick(C.byref(beam.struct()), counts.data_ptr(), nbins, rng.data_ptr(),
                                C.byref(w), p_ref, mode, ws.ptr, ws.nbytes, _stream_handle(stream)))
+
+
+def dipole_histogram(beam: Beam, nbins: int, ws: Workspace, stream=None):
+    """(range[2], counts[nbins], dipole[2][nbins] int64 in units of 2^-40 m)."""
+    import torch
+    dev = beam.z.device
+    rng = torch.empty(2, dtype=torch.float64, device=dev)
+    cnt = torch.empty(nbins, dtype=torch.int32, device=dev)
+    dip = torch.empty((2, nbins), dtype=torch.int64, device=dev)
+    _check(lib().trk_dipole_histogram(C.byref(beam.struct()), nbins, rng.data_ptr(),
+                                      cnt.data_ptr(), dip.data_ptr(), ws.ptr, ws.nbytes,
+                                      _stream_handle(stream)))
+    return rng, cnt, dip
+
+
+def trwake_convolve(dip, nbins: int, rng, tau0: float, omega: float, mode: int, stream=None):
+    import torch
+    v = torch.empty((2, nbins), dtype=torch.float64, device=rng.device)
+    _check(lib().trk_trwake_convolve(dip.data_ptr(), nbins, rng.data_ptr(), tau0, omega, mode,
+                                     v.data_ptr(), _stream_handle(stream)))
+    return v
+
+
+def trwake_kick(beam: Beam, dip, nbins: int, rng, A: float, tau0: float, omega: float,
+                charge: float, p_ref: float, mode: int, ws: Workspace, stream=None) -> None:
+    w = Wake(A, tau0, omega, charge)
+    _check(lib().trk_trwake_kick(C.byref(beam.struct()), dip.data_ptr(), nbins, rng.data_ptr(),
+                                 C.byref(w), p_ref, mode, ws.ptr, ws.nbytes,
+                                 _stream_handle(stream)))
 
 
 def moments(beam: Beam, ws: Workspace, stream=None):

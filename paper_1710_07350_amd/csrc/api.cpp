@@ -230,6 +230,7 @@ bool matches(const double *c, const Term *pat, int n, std::vector<double> &out) 
 
 constexpr uint32_t M_X = 1, M_XP = 2, M_Y = 4, M_YP = 8, M_S = 16, M_DP = 32, M_ID = 64;
 constexpr uint32_t M_ALL = 63;
+constexpr double kStreamBytes = 256.0 * 1024 * 1024;  // MI355X Infinity Cache
 
 }  // namespace
 
@@ -379,6 +380,18 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
         rd = M_S | M_DP;
         wr = M_DP;
         break;
+      case TRK_TRWAKE:
+        if (s.nbins < 2 || s.nbins > TRK_MAX_TRBINS)
+          return bad("TRWAKE nbins must be 2..TRK_MAX_TRBINS");
+        if (!(s.wake_tau0 > 0.0)) return bad("TRWAKE needs tau0 > 0");
+        d.kind = K_TRWAKE;
+        d.ip = s.nbins;
+        d.vslot = L->nvar++;
+        L->has_wake = true;
+        L->max_bins = std::max(L->max_bins, s.nbins);
+        rd = M_XP | M_YP | M_S | M_DP;
+        wr = M_XP | M_YP;
+        break;
       case TRK_RADKICK:
         d.kind = K_RADKICK;
         d.p0 = s.sigma;
@@ -464,10 +477,12 @@ Workspace carve(void *base, int64_t n_total, size_t *bytes) {
   Carver c{static_cast<char *>(base)};
   Workspace w;
   w.mm_part = c.take<double>(2 * std::max<size_t>(nb, kMaxRunGrid));
-  w.counts = c.take<uint32_t>(TRK_MAX_BINS + 64);
+  w.counts = c.take<uint32_t>(TRK_MAX_BINS + 64 + 4 * TRK_MAX_TRBINS);
+  w.dip = base ? reinterpret_cast<int64_t *>(w.counts + TRK_MAX_BINS + 64) : nullptr;
+  w.lost_flag = c.take<uint32_t>((n + 63) / 64);
   w.range = c.take<double>(2);
   w.wake_par = c.take<double>(2);
-  w.wake_v = c.take<double>(TRK_MAX_BINS);
+  w.wake_v = c.take<double>(2 * TRK_MAX_BINS);
   w.mom_shift = c.take<double>(6);
   w.mom_tmp = c.take<double>(28);
   w.mom_part = c.take<double>(static_cast<size_t>(kMomPassesMax) * std::max<size_t>(nb, 1024) * 28);
@@ -500,6 +515,14 @@ extern "C" size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total) {
 }
 
 namespace {
+
+bool is_wake(int32_t kind) { return kind == TRK_WAKE || kind == TRK_TRWAKE; }
+
+// words of the counts region to clear before a histogram: the counts, and
+// for a transverse wake the dipole sums that follow them
+int zero_words(bool transverse) {
+  return transverse ? TRK_MAX_BINS + 64 + 4 * TRK_MAX_TRBINS : TRK_MAX_BINS;
+}
 
 int grid_stride_blocks(int64_t n_total) {
   const int64_t nb = nblocks(n_total);
@@ -545,7 +568,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
           vconst[2 * (static_cast<size_t>(p) * lat->nvar + v)] = P;
           vconst[2 * (static_cast<size_t>(p) * lat->nvar + v) + 1] = 1.0 / pn;
           P = pn;
-        } else if (s.kind == TRK_WAKE) {
+        } else if (s.kind == TRK_WAKE || s.kind == TRK_TRWAKE) {
           const double kfac = ((s.charge / static_cast<double>(beam->n_total)) * s.wake_A) / P;
           vconst[2 * (static_cast<size_t>(p) * lat->nvar + v)] = kfac;
         }
@@ -572,7 +595,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
       while (e0 < nelem) {
         int e1 = e0 + 1;
         // extend up to the next wake, the element limit and the constant slots
-        while (e1 < nelem && lat->src[e1].kind != TRK_WAKE && e1 - e0 < max_e &&
+        while (e1 < nelem && !is_wake(lat->src[e1].kind) && e1 - e0 < max_e &&
                nvar_in(e0, e1 + 1) <= kMaxVar)
           ++e1;
         plan.push_back({p, 1, e0, e1});
@@ -598,8 +621,9 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   bool dirty = false;
   for (size_t li = 0; li < plan.size(); ++li) {
     const Launch &L = plan[li];
-    const bool starts_wake = lat->src[L.e0].kind == TRK_WAKE;
+    const bool starts_wake = is_wake(lat->src[L.e0].kind);
     if (starts_wake) {
+      const bool tr = lat->src[L.e0].kind == TRK_TRWAKE;
       if (dirty) {
         HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
                 "compact");
@@ -609,26 +633,34 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
       if (prev_mm_n == 0) {
         prev_mm_n = grid_stride_blocks(beam->n_total);
         HIP_TRY(launch_minmax(beam->s, beam->n_alive, beam->n_total, w.mm_part, prev_mm_n, w.counts,
-                              TRK_MAX_BINS, st),
+                              zero_words(tr), st),
                 "minmax");
       }
       HIP_TRY(profiled(2, st,
                        [&] {
                          return launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part,
-                                                 prev_mm_n, nb, w.counts, w.range, st);
+                                                 prev_mm_n, nb, w.counts, w.range, st,
+                                                 tr ? beam->x : nullptr, tr ? beam->y : nullptr,
+                                                 tr ? w.dip : nullptr);
                        }),
               "histogram");
       HIP_TRY(profiled(3, st,
                        [&] {
-                         return launch_convolve(w.counts, nb, w.range, lat->src[L.e0].wake_tau0,
-                                                lat->src[L.e0].wake_omega, opts->wake_mode,
-                                                w.wake_v, w.wake_par, st);
+                         const trk_element &s = lat->src[L.e0];
+                         if (tr)
+                           return launch_convolve_tr(w.dip, nb, w.range, s.wake_tau0, s.wake_omega,
+                                                     opts->wake_mode, w.wake_v, w.wake_par, st);
+                         return launch_convolve(w.counts, nb, w.range, s.wake_tau0, s.wake_omega,
+                                                opts->wake_mode, w.wake_v, w.wake_par, st);
                        }),
               "convolve");
     }
     // does the next launch start with a wake?
-    bool next_wake = false;
-    if (li + 1 < plan.size()) next_wake = lat->src[plan[li + 1].e0].kind == TRK_WAKE;
+    bool next_wake = false, next_tr = false;
+    if (li + 1 < plan.size()) {
+      next_wake = is_wake(lat->src[plan[li + 1].e0].kind);
+      next_tr = lat->src[plan[li + 1].e0].kind == TRK_TRWAKE;
+    }
     const bool lmom = mom && L.e1 == nelem;
 
     RunArgs a;
@@ -654,7 +686,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         case K_KQUAD:
         case K_CSBEND: feat |= F_KD; break;
         case K_RFCA: feat |= F_RF; break;
-        case K_WAKE: feat |= F_WAKE; break;
+        case K_WAKE:
+        case K_TRWAKE: feat |= F_WAKE; break;
         case K_RADKICK: feat |= F_RNG; break;
         case K_MAP2_GEN: feat |= F_GEN; break;
         default: break;
@@ -687,13 +720,26 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
     a.mom_part = w.mom_part;
     a.mom_shift = w.mom_shift;
     a.chk_lost = dirty ? 1 : 0;
+    a.lost_flag = w.lost_flag;
+    if (any_aper && !dirty) {
+      // the first run since the call began or since the last compaction
+      // that can lose particles: it raises the flags of its losses
+      HIP_TRY(launch_zero_u32(w.lost_flag, static_cast<int>((beam->n_total + 63) / 64), st),
+              "loss flags");
+    }
     a.longit = opts->run_longit >= 0 && !lmom && !any_aper && !dirty &&
                ((a.ldmask | a.stmask) & ~(M_S | M_DP)) == 0 && (feat & ~(F_RF | F_WAKE)) == 0;
+    // Stream with non-temporal accesses when the coordinates a run touches
+    // exceed the 256 MB Infinity Cache: they cannot stay resident for the
+    // next launch anyway.
+    const double touched =
+        8.0 * __builtin_popcount((a.ldmask | a.stmask) & M_ALL) * static_cast<double>(beam->n_total);
+    a.nt = opts->run_nt > 0 ? 1 : (opts->run_nt < 0 ? 0 : (touched > kStreamBytes ? 1 : 0));
     const int grid = run_shape(a, beam->n_total, opts->run_ppt, opts->run_blocks);
     if (next_wake) {
       a.mm_part = w.mm_part;
       a.zero_buf = w.counts;
-      a.zero_n = TRK_MAX_BINS;
+      a.zero_n = zero_words(next_tr);
     }
     HIP_TRY(profiled(0, st, [&] { return launch_run(a, grid, st); }), "run kernel");
     prev_mm_n = next_wake ? grid : 0;
@@ -766,6 +812,72 @@ extern "C" int trk_wake_kick(trk_beam *beam, const uint32_t *counts_dev, int32_t
   HIP_TRY(launch_wake_kick(beam->s, beam->dp, beam->n_alive, beam->n_total, w.wake_v, w.wake_par,
                            nbins, kfac, st),
           "wake kick");
+  return TRK_OK;
+}
+
+extern "C" int trk_dipole_histogram(const trk_beam *beam, int32_t nbins, double *range_dev,
+                                    uint32_t *counts_dev, int64_t *dipole_dev, void *workspace,
+                                    size_t workspace_bytes_, void *stream) {
+  if (nbins < 2 || nbins > TRK_MAX_TRBINS)
+    return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_TRBINS");
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_dev(counts_dev, "counts")) return r;
+  if (int r = check_dev(dipole_dev, "dipole")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  const int g = grid_stride_blocks(beam->n_total);
+  HIP_TRY(launch_zero_u32(reinterpret_cast<uint32_t *>(dipole_dev), 4 * nbins, st), "zero");
+  HIP_TRY(launch_minmax(beam->s, beam->n_alive, beam->n_total, w.mm_part, g, counts_dev, nbins, st),
+          "minmax");
+  HIP_TRY(launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part, g, nbins, counts_dev,
+                           range_dev, st, beam->x, beam->y, dipole_dev),
+          "dipole histogram");
+  return TRK_OK;
+}
+
+extern "C" int trk_trwake_convolve(const int64_t *dipole_dev, int32_t nbins,
+                                   const double *range_dev, double tau0, double omega,
+                                   int32_t mode, double *v_dev, void *stream) {
+  if (nbins < 2 || nbins > TRK_MAX_TRBINS)
+    return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_TRBINS");
+  if (mode != TRK_WAKE_FP64 && mode != TRK_WAKE_FP32_MFMA) return fail(TRK_EINVAL, "unknown mode");
+  if (!(tau0 > 0.0)) return fail(TRK_EINVAL, "tau0 must be > 0");
+  if (int r = check_dev(dipole_dev, "dipole")) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_dev(v_dev, "v")) return r;
+  HIP_TRY(launch_convolve_tr(dipole_dev, nbins, range_dev, tau0, omega, mode, v_dev, nullptr,
+                             static_cast<hipStream_t>(stream)),
+          "convolve");
+  return TRK_OK;
+}
+
+extern "C" int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
+                               const double *range_dev, const trk_wake *wk, double p_ref_eV,
+                               int32_t mode, void *workspace, size_t workspace_bytes_,
+                               void *stream) {
+  if (wk == nullptr) return fail(TRK_EINVAL, "wake is NULL");
+  if (nbins < 2 || nbins > TRK_MAX_TRBINS)
+    return fail(TRK_ERANGE, "nbins must be 2..TRK_MAX_TRBINS");
+  if (mode != TRK_WAKE_FP64 && mode != TRK_WAKE_FP32_MFMA) return fail(TRK_EINVAL, "unknown mode");
+  if (!(wk->tau0 > 0.0)) return fail(TRK_EINVAL, "tau0 must be > 0");
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(dipole_dev, "dipole")) return r;
+  if (int r = check_dev(range_dev, "range")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  if (beam->n_total == 0) return TRK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  HIP_TRY(launch_convolve_tr(dipole_dev, nbins, range_dev, wk->tau0, wk->omega, mode, w.wake_v,
+                             w.wake_par, st),
+          "convolve");
+  const double kfac = ((wk->charge / static_cast<double>(beam->n_total)) * wk->A) / p_ref_eV;
+  double *z[6];
+  beam_ptrs(beam, z);
+  HIP_TRY(launch_trwake_kick(z, beam->n_alive, beam->n_total, w.wake_v, w.wake_par, nbins, kfac,
+                             st),
+          "transverse wake kick");
   return TRK_OK;
 }
 
@@ -856,7 +968,7 @@ extern "C" int trk_batch_create(const trk_lattice *const *lats, int32_t nvar, co
         delete B;
         return fail(TRK_EINVAL, "batch lattices must have the same element kinds");
       }
-      if (L->src[e].kind == TRK_RFCA || L->src[e].kind == TRK_WAKE) {
+      if (L->src[e].kind == TRK_RFCA || is_wake(L->src[e].kind)) {
         delete B;
         return fail(TRK_EINVAL, "RF cavities and wakes are not supported in batches");
       }

@@ -73,6 +73,15 @@ __device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const El
         z[5] = fma(-cx.vc[v][0], vs, z[5]);
       }
       break;
+    case K_TRWAKE:
+      if constexpr ((kFeat & F_WAKE) != 0) {
+        const int v = p * cx.nv + (E.vslot - cx.v0);
+        const double ux = el::wake_interp(z[4], cx.wake_par[0], cx.wake_par[1], cx.wake_v, E.ip);
+        const double uy =
+            el::wake_interp(z[4], cx.wake_par[0], cx.wake_par[1], cx.wake_v + E.ip, E.ip);
+        el::trwake(z, cx.vc[v][0], ux, uy);
+      }
+      break;
     case K_RADKICK:
       if constexpr ((kFeat & F_RNG) != 0) radkick_call(z[5], E.p0, pid, gp, cx.seed_lo, cx.seed_hi);
       break;

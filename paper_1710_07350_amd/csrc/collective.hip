@@ -1,6 +1,8 @@
 // collective.hip -- the cross-particle steps: range of s, histogram, wake
 // convolution (binary64 sequential and FP32 matrix-core), wake kick and beam
 // moments.
+#include <type_traits>
+
 #include "elements.h"
 #include "reduce.h"
 
@@ -46,14 +48,27 @@ hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_tota
 // order, so no extra launch is needed.
 constexpr int kHistThreads = 1024;
 
-__global__ __launch_bounds__(kHistThreads) void k_histogram(const double *__restrict__ s,
-                                                            const int64_t *__restrict__ n_alive,
-                                                            const double *__restrict__ mm_part,
-                                                            int mm_n, int nbins, int nsub,
-                                                            uint32_t *__restrict__ counts,
-                                                            double *__restrict__ range) {
-  extern __shared__ uint32_t sub[];  // [nsub][nbins]
+// A transverse coordinate as an integer multiple of 2^-40 m (clamped to
+// [-1, 1] m, ties to even, NaN counts 0), as a two's-complement word: sums of
+// these words modulo 2^64 are exact and independent of their order.
+__device__ __forceinline__ unsigned long long dip_quantum(double x) {
+  if (x != x) return 0ull;
+  x = x > 1.0 ? 1.0 : (x < -1.0 ? -1.0 : x);
+  return static_cast<unsigned long long>(static_cast<long long>(__builtin_rint(x * 0x1p40)));
+}
+
+// kDip: the same histogram, plus per bin the sums of the quantised x and y
+// (LDS sub-histograms of 64-bit words after the counts).
+template <bool kDip>
+__global__ __launch_bounds__(kHistThreads) void k_histogram(
+    const double *__restrict__ s, const double *__restrict__ xs, const double *__restrict__ ys,
+    const int64_t *__restrict__ n_alive, const double *__restrict__ mm_part, int mm_n, int nbins,
+    int nsub, uint32_t *__restrict__ counts, unsigned long long *__restrict__ dip,
+    double *__restrict__ range) {
+  extern __shared__ uint32_t sub[];  // [nsub][nbins] counts; kDip: then [nsub][2][nbins] words
   __shared__ double pm[kHistThreads / 64][2];
+  unsigned long long *subd =
+      reinterpret_cast<unsigned long long *>(sub + ((nsub * nbins + 1) & ~1));
   const int64_t n = *n_alive;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
@@ -71,6 +86,8 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const double *__rest
     pm[wave][1] = mx;
   }
   for (int j = threadIdx.x; j < nsub * nbins; j += kHistThreads) sub[j] = 0u;
+  if constexpr (kDip)
+    for (int j = threadIdx.x; j < 2 * nsub * nbins; j += kHistThreads) subd[j] = 0ull;
   __syncthreads();
   mn = pm[0][0];
   mx = pm[0][1];
@@ -89,18 +106,33 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const double *__rest
   const double width = mx - mn;
   const double inv = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
   uint32_t *mine = sub + (wave % nsub) * nbins;
+  unsigned long long *mined = subd + 2 * (wave % nsub) * nbins;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kHistThreads;
   // four loads in flight per thread
   constexpr int kU = 4;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kHistThreads + threadIdx.x; i < n;
        i += kU * stride) {
-    double v[kU];
+    double v[kU], vx[kU], vy[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = i + u * stride < n ? s[i + u * stride] : -1.0;
+    for (int u = 0; u < kU; ++u) {
+      const bool in = i + u * stride < n;
+      v[u] = in ? s[i + u * stride] : -1.0;
+      if constexpr (kDip) {
+        vx[u] = in ? xs[i + u * stride] : 0.0;
+        vy[u] = in ? ys[i + u * stride] : 0.0;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const double f = (v[u] - mn) * inv;
-      if (i + u * stride < n && f >= 0.0) atomicAdd(mine + min(static_cast<int>(f), nbins - 1), 1u);
+      if (i + u * stride < n && f >= 0.0) {
+        const int b = min(static_cast<int>(f), nbins - 1);
+        atomicAdd(mine + b, 1u);
+        if constexpr (kDip) {
+          atomicAdd(mined + b, dip_quantum(vx[u]));
+          atomicAdd(mined + nbins + b, dip_quantum(vy[u]));
+        }
+      }
     }
   }
   __syncthreads();
@@ -108,82 +140,122 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(const double *__rest
     uint32_t c = 0;
     for (int w = 0; w < nsub; ++w) c += sub[w * nbins + b];
     if (c != 0u) atomicAdd(counts + b, c);
+    if constexpr (kDip) {
+      unsigned long long sx = 0ull, sy = 0ull;
+      for (int w = 0; w < nsub; ++w) {
+        sx += subd[2 * w * nbins + b];
+        sy += subd[(2 * w + 1) * nbins + b];
+      }
+      if (sx != 0ull) atomicAdd(dip + b, sx);
+      if (sy != 0ull) atomicAdd(dip + nbins + b, sy);
+    }
   }
 }
 
 hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
                             const double *mm_part, int mm_n, int nbins, uint32_t *counts,
-                            double *range, hipStream_t st) {
+                            double *range, hipStream_t st, const double *x, const double *y,
+                            int64_t *dip) {
   const int64_t want = (n_total + kHistThreads * 32 - 1) / (kHistThreads * 32);
   const int grid = static_cast<int>(want < 1 ? 1 : (want > 256 ? 256 : want));
+  const bool d = dip != nullptr;
+  // bytes of one sub-histogram; sub-histograms share at most 32 KB (48 KB
+  // with the dipole words)
+  const size_t per = static_cast<size_t>(nbins) * (d ? 20 : 4);
+  const size_t budget = d ? 49152 : 32768;
   int nsub = kHistThreads / 64;
-  while (nsub > 1 && static_cast<size_t>(nsub) * nbins * sizeof(uint32_t) > 32768) nsub >>= 1;
-  const size_t lds = sizeof(uint32_t) * nsub * nbins;
-  hipLaunchKernelGGL(k_histogram, dim3(grid), dim3(kHistThreads), lds, st, s, n_alive, mm_part,
-                     mm_n, nbins, nsub, counts, range);
+  while (nsub > 1 && static_cast<size_t>(nsub) * per > budget) nsub >>= 1;
+  if (static_cast<size_t>(nsub) * per > budget) return hipErrorInvalidValue;
+  const size_t lds = static_cast<size_t>(nsub) * per + (d ? 8 : 0);
+  auto *du = reinterpret_cast<unsigned long long *>(dip);
+  if (d)
+    hipLaunchKernelGGL(k_histogram<true>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
+                       n_alive, mm_part, mm_n, nbins, nsub, counts, du, range);
+  else
+    hipLaunchKernelGGL(k_histogram<false>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
+                       n_alive, mm_part, mm_n, nbins, nsub, counts, du, range);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ convolution
-// Normalised resonator wake on the bin lags: W~[0] = 1/2 (a particle sees
-// half of its own wake), W~[m] = exp(-t/tau0) cos(omega t), t = m * delta / c.
+// Normalised resonator wakes on the bin lags t = m * delta / c:
+//   longitudinal W~[0] = 1/2 (a particle sees half of its own wake),
+//                W~[m] = exp(-t/tau0) cos(omega t);
+//   transverse   Wt[0] = 0,  Wt[m] = exp(-t/tau0) sin(omega t).
+template <bool kTr>
 __device__ __forceinline__ double wake_table_entry(int m, double dt, double tau0, double omega) {
-  if (m == 0) return 0.5;
+  if (m == 0) return kTr ? 0.0 : 0.5;
   const double t = static_cast<double>(m) * dt;
-  return dm::own_exp(-(t / tau0)) * dm::own_cos(omega * t);
+  return dm::own_exp(-(t / tau0)) * (kTr ? dm::own_sin(omega * t) : dm::own_cos(omega * t));
+}
+
+// Convolution weights: the counts, or (transverse, plane blockIdx.y) the
+// dipole sums in metres, 2^-40 times the integer (one rounding).
+template <bool kTr>
+__device__ __forceinline__ double conv_weight(const void *src, int nbins, int m) {
+  if constexpr (kTr)
+    return static_cast<double>(static_cast<const long long *>(src)[blockIdx.y * nbins + m]) * 0x1p-40;
+  else
+    return static_cast<double>(static_cast<const uint32_t *>(src)[m]);
 }
 
 constexpr int kTile = 256;  // outputs per convolution workgroup
 
 __device__ __forceinline__ void write_wake_par(double smin, double width, int nbins,
                                                double *wake_par) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && wake_par != nullptr) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && wake_par != nullptr) {
     wake_par[0] = smin;
     wake_par[1] = width > 0.0 ? static_cast<double>(nbins) / width : 0.0;
   }
 }
 
-// Binary64: V[i] = sum_{j<=i} c_j W~[i-j], j ascending, one fma chain per
+// Binary64: V[i] = sum_{j<=i} c_j W[i-j], j ascending, one fma chain per
 // output -- the plain causal convolution, bit-exact with a sequential CPU
-// loop.  Workgroup g owns outputs [256 g, 256 g + 256).
-__global__ __launch_bounds__(kTile) void k_conv_fp64(const uint32_t *__restrict__ counts, int nbins,
+// loop.  Workgroup g owns outputs [256 g, 256 g + 256) (of plane blockIdx.y).
+template <bool kTr>
+__global__ __launch_bounds__(kTile) void k_conv_fp64(const void *__restrict__ src, int nbins,
                                                      const double *__restrict__ range, double tau0,
                                                      double omega, double *__restrict__ v,
                                                      double *__restrict__ wake_par) {
-  __shared__ double W[TRK_MAX_BINS];
-  __shared__ uint32_t C[TRK_MAX_BINS];
+  constexpr int kN = kTr ? TRK_MAX_TRBINS : TRK_MAX_BINS;
+  __shared__ double W[kN];
+  __shared__ std::conditional_t<kTr, double, uint32_t> C[kN];
   const double smin = range[0], smax = range[1];
   const double width = smax - smin;
   const double delta = width > 0.0 ? width / static_cast<double>(nbins) : 0.0;
   const double dt = delta / kCLight;
   const int hi = min(nbins, kTile * static_cast<int>(blockIdx.x + 1));
   for (int m = threadIdx.x; m < hi; m += kTile) {
-    W[m] = wake_table_entry(m, dt, tau0, omega);
-    C[m] = counts[m];
+    W[m] = wake_table_entry<kTr>(m, dt, tau0, omega);
+    if constexpr (kTr)
+      C[m] = conv_weight<kTr>(src, nbins, m);
+    else
+      C[m] = static_cast<const uint32_t *>(src)[m];
   }
   __syncthreads();
   const int i = kTile * blockIdx.x + threadIdx.x;
   if (i < nbins) {
     double acc = 0.0;
     for (int j = 0; j <= i; ++j) acc = fma(static_cast<double>(C[j]), W[i - j], acc);
-    v[i] = acc;
+    v[blockIdx.y * nbins + i] = acc;
   }
   write_wake_par(smin, width, nbins, wake_par);
 }
 
 // FP32 on the matrix cores.  With V, c laid out as 16-row matrices
 // Vm[b][a] = V[16a+b], the causal convolution is a sum of products of
-// lower-Toeplitz 16x16 tiles T_d[b][b'] = W~[16d+b-b'] with column-shifted
-// count tiles S_d[b'][a] = c[16(a-d)+b']:  Vm = sum_d T_d S_d, a dense
+// lower-Toeplitz 16x16 tiles T_d[b][b'] = W[16d+b-b'] with column-shifted
+// weight tiles S_d[b'][a] = c[16(a-d)+b']:  Vm = sum_d T_d S_d, a dense
 // contraction that v_mfma_f32_16x16x4_f32 executes.  Workgroup g owns the
 // 16 columns (256 outputs) of tile g and needs d < 16g + 16; its 16 waves
 // split d and their partial tiles are added in wave order (deterministic).
-// W~ and c are rounded once to binary32 (c is exact below 2^24).
+// W and c are rounded once to binary32 (counts are exact below 2^24).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kConvWaves = 16;
 
+template <bool kTr>
 __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
-    const uint32_t *__restrict__ counts, int nbins, const double *__restrict__ range, double tau0,
+    const void *__restrict__ src, int nbins, const double *__restrict__ range, double tau0,
     double omega, double *__restrict__ v, double *__restrict__ wake_par) {
   __shared__ float Wf[TRK_MAX_BINS];
   __shared__ float Cf[TRK_MAX_BINS];
@@ -195,8 +267,8 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
   const int g = blockIdx.x;
   const int hi = kTile * (g + 1);  // entries this tile can touch
   for (int m = threadIdx.x; m < hi; m += blockDim.x) {
-    Wf[m] = m < nbins ? static_cast<float>(wake_table_entry(m, dt, tau0, omega)) : 0.0f;
-    Cf[m] = m < nbins ? static_cast<float>(counts[m]) : 0.0f;
+    Wf[m] = m < nbins ? static_cast<float>(wake_table_entry<kTr>(m, dt, tau0, omega)) : 0.0f;
+    Cf[m] = m < nbins ? static_cast<float>(conv_weight<kTr>(src, nbins, m)) : 0.0f;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -222,21 +294,33 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
 #pragma unroll
     for (int w = 1; w < kConvWaves; ++w) sum += part[w][threadIdx.x];
     const int i = kTile * g + threadIdx.x;
-    if (i < nbins) v[i] = static_cast<double>(sum);
+    if (i < nbins) v[blockIdx.y * nbins + i] = static_cast<double>(sum);
   }
   write_wake_par(smin, width, nbins, wake_par);
 }
 
+template <bool kTr>
+hipError_t launch_conv(const void *src, int nbins, const double *range, double tau0, double omega,
+                       int mode, double *v, double *wake_par, hipStream_t st) {
+  const dim3 grid((nbins + kTile - 1) / kTile, kTr ? 2 : 1);
+  if (mode == TRK_WAKE_FP32_MFMA)
+    hipLaunchKernelGGL(k_conv_mfma<kTr>, grid, dim3(64 * kConvWaves), 0, st, src, nbins, range,
+                       tau0, omega, v, wake_par);
+  else
+    hipLaunchKernelGGL(k_conv_fp64<kTr>, grid, dim3(kTile), 0, st, src, nbins, range, tau0, omega,
+                       v, wake_par);
+  return hipGetLastError();
+}
+
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
                            double omega, int mode, double *v, double *wake_par, hipStream_t st) {
-  const int tiles = (nbins + kTile - 1) / kTile;
-  if (mode == TRK_WAKE_FP32_MFMA)
-    hipLaunchKernelGGL(k_conv_mfma, dim3(tiles), dim3(64 * kConvWaves), 0, st, counts, nbins,
-                       range, tau0, omega, v, wake_par);
-  else
-    hipLaunchKernelGGL(k_conv_fp64, dim3(tiles), dim3(kTile), 0, st, counts, nbins, range, tau0,
-                       omega, v, wake_par);
-  return hipGetLastError();
+  return launch_conv<false>(counts, nbins, range, tau0, omega, mode, v, wake_par, st);
+}
+
+hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range, double tau0,
+                              double omega, int mode, double *v, double *wake_par,
+                              hipStream_t st) {
+  return launch_conv<true>(dip, nbins, range, tau0, omega, mode, v, wake_par, st);
 }
 
 // ------------------------------------------------------------------ wake kick
@@ -262,6 +346,37 @@ hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64
   const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxRunGrid ? kMaxRunGrid : want));
   hipLaunchKernelGGL(k_wake_kick, dim3(grid), dim3(kBlock), 0, st, s, dp, n_alive, v, wake_par,
                      nbins, kfac);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ transverse wake kick
+__global__ __launch_bounds__(kBlock) void k_trwake_kick(double *__restrict__ xp,
+                                                        double *__restrict__ yp,
+                                                        const double *__restrict__ s,
+                                                        const double *__restrict__ dp,
+                                                        const int64_t *__restrict__ n_alive,
+                                                        const double *__restrict__ v,
+                                                        const double *__restrict__ wake_par,
+                                                        int nbins, double kfac) {
+  const int64_t n = *n_alive;
+  const double smin = wake_par[0], inv = wake_par[1];
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double z[6] = {0.0, xp[i], 0.0, yp[i], s[i], dp[i]};
+    el::trwake(z, kfac, el::wake_interp(z[4], smin, inv, v, nbins),
+               el::wake_interp(z[4], smin, inv, v + nbins, nbins));
+    xp[i] = z[1];
+    yp[i] = z[3];
+  }
+}
+
+hipError_t launch_trwake_kick(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                              const double *v, const double *wake_par, int nbins, double kfac,
+                              hipStream_t st) {
+  const int64_t want = nblocks(n_total);
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxRunGrid ? kMaxRunGrid : want));
+  hipLaunchKernelGGL(k_trwake_kick, dim3(grid), dim3(kBlock), 0, st, z[1], z[3], z[4], z[5],
+                     n_alive, v, wake_par, nbins, kfac);
   return hipGetLastError();
 }
 
@@ -352,7 +467,8 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, p, n);
+  const int g = n <= kBlock ? 1 : (n / kBlock > 1024 ? 1024 : (n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(kBlock), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 //           kick Delta px = -l h (1 + hx).
 //   RFCA    zero-length cavity: delta <- (delta P + V (cos(phi+ks) - cos phi))/P',
 //           P' = P + V cos phi, the difference as -2 sin(phi+ks/2) sin(ks/2).
+//   TRWAKE  canonical px, py gain kfac V_x(s), kfac V_y(s) (as in MULT).
 #pragma once
 #include "devmath.h"
 #include "trk_internal.h"
@@ -149,6 +150,14 @@ __device__ __forceinline__ void mult(double (&z)[6], double kn, int order) {
   }
   c.px = fma(-kn, re, c.px);
   c.py = fma(kn, im, c.py);
+  slopes(z, c);
+}
+
+// TRWAKE: the canonical momenta gain kfac V_x and kfac V_y
+__device__ __forceinline__ void trwake(double (&z)[6], double kfac, double ux, double uy) {
+  Canon c = canonical(z);
+  c.px = fma(kfac, ux, c.px);
+  c.py = fma(kfac, uy, c.py);
   slopes(z, c);
 }
 

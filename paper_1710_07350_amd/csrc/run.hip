@@ -33,8 +33,9 @@ namespace trk {
 // only s and delta (RF cavities, wake kicks, longitudinal maps), so only
 // those two coordinates are loaded and kept in registers.  The moments
 // variant makes one pass over the grid with kP particles per thread, so
-// that every thread reaches the per-pass block reductions.
-template <uint32_t kFeat, bool kMom, int kP, bool kLong>
+// that every thread reaches the per-pass block reductions.  kNT: the
+// coordinates are streamed with non-temporal loads and stores.
+template <uint32_t kFeat, bool kMom, int kP, bool kLong, bool kNT = false>
 __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
   const ConstElems elems = (ConstElems)a.elems;
   const ConstPool pool = (ConstPool)a.pool;
@@ -61,7 +62,10 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         const bool want = kLong ? (k >= 4) : ((a.ldmask >> k) & 1u) != 0;
-        z[q][k] = (inb && want) ? a.z[k][i] : 0.0;
+        if constexpr (kNT)
+          z[q][k] = (inb && want) ? __builtin_nontemporal_load(a.z[k] + i) : 0.0;
+        else
+          z[q][k] = (inb && want) ? a.z[k][i] : 0.0;
       }
       pid[q] = (!kLong && inb && ((a.ldmask >> 6) & 1u)) ? a.id[i] : 0u;
     }
@@ -69,8 +73,15 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
     for (int q = 0; q < kP; ++q) {
       act[q] = base + q * nthr < n;
       if constexpr (!kLong) {
-        // a particle lost earlier in the same call still holds its slot
-        if (a.chk_lost && act[q]) act[q] = a.lost_at[base + q * nthr] < 0;
+        // A particle lost earlier in the same call still holds its slot.  The
+        // 64 slots of a wave share one loss flag (a wave-uniform load); only
+        // flagged groups read the loss records.
+        if (a.chk_lost) {
+          int64_t g = __builtin_amdgcn_readfirstlane(static_cast<int>((base + q * nthr) >> 6));
+          const int64_t glast = ntot > 0 ? (ntot - 1) >> 6 : 0;
+          g = g < 0 ? 0 : (g < glast ? g : glast);  // in bounds even with no lane active
+          if (act[q] && a.lost_flag[g] != 0u) act[q] = a.lost_at[base + q * nthr] < 0;
+        }
       }
       alive[q] = act[q];
       rec[q] = -1;
@@ -106,8 +117,16 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       const int64_t i = base + q * nthr;
 #pragma unroll
       for (int k = kLong ? 4 : 0; k < 6; ++k)
-        if ((a.stmask >> k) & 1u) a.z[k][i] = z[q][k];
-      if (!kLong && rec[q] >= 0) a.lost_at[i] = rec[q];
+        if ((a.stmask >> k) & 1u) {
+          if constexpr (kNT)
+            __builtin_nontemporal_store(z[q][k], a.z[k] + i);
+          else
+            a.z[k][i] = z[q][k];
+        }
+      if (!kLong && rec[q] >= 0) {
+        a.lost_at[i] = rec[q];
+        a.lost_flag[i >> 6] = 1u;
+      }
       if (alive[q]) {
         smin = fmin(smin, z[q][4]);
         smax = fmax(smax, z[q][4]);
@@ -131,14 +150,22 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
 constexpr bool light(uint32_t f) { return (f & (F_KD | F_RNG | F_GEN)) == 0; }
 constexpr bool longit_ok(uint32_t f) { return (f & ~(F_RF | F_WAKE)) == 0; }
 
+template <uint32_t kFeat, bool kLong, bool kNT>
+void launch_ppt_nt(const RunArgs &a, int grid, hipStream_t st) {
+  switch (a.ppt) {
+    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+  }
+}
+
 template <uint32_t kFeat, bool kLong>
 void launch_ppt(const RunArgs &a, int grid, hipStream_t st) {
-  switch (a.ppt) {
-    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong>), dim3(grid), dim3(kBlock), 0, st, a); break;
-  }
+  if (a.nt)
+    launch_ppt_nt<kFeat, kLong, true>(a, grid, st);
+  else
+    launch_ppt_nt<kFeat, kLong, false>(a, grid, st);
 }
 
 template <uint32_t kFeat>
@@ -166,7 +193,6 @@ void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
 }
 
 int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req) {
-  const int64_t nb = nblocks(n_total);
   if (a.mom) {
     // every thread reaches the per-pass block reductions: no grid stride
     a.ppt = ppt_req >= 2 ? 2 : 1;
@@ -178,7 +204,9 @@ int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req) {
   ppt = ppt >= 8 ? 8 : (ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1));
   a.ppt = ppt;
   const int64_t want = (n_total + static_cast<int64_t>(kBlock) * ppt - 1) / (kBlock * ppt);
-  const int64_t cap = cap_req > 0 ? cap_req : (a.longit ? kLongRunGrid : kMaxRunGrid);
+  // light runs cover the array in one sweep of the grid; the others stride
+  const int64_t cap = cap_req > 0 ? cap_req
+                                  : (a.longit ? kLongRunGrid : (light(a.feat) ? want : kMaxRunGrid));
   return static_cast<int>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 

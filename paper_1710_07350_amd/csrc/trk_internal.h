@@ -13,7 +13,7 @@ constexpr int kBlock = 256;        // threads per block of the particle kernels
 constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
 constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
-constexpr int kLightPPT = 4;       // particles per thread of memory-bound runs
+constexpr int kLightPPT = 2;       // particles per thread of memory-bound runs
 constexpr int kLongPPT = 2;        // ... of runs that touch only s and delta
 constexpr int kLongRunGrid = 1024; // grid-stride cap of those runs (4 blocks per CU)
 constexpr int kMaxRunGrid = 4096;  // grid-stride cap of the run kernel
@@ -33,6 +33,7 @@ enum DevKind : int32_t {
   K_WAKE = 9,
   K_RADKICK = 10,
   K_MARKER = 11,
+  K_TRWAKE = 12,
 };
 
 // Element families present in a run; the run kernel is instantiated per set
@@ -58,8 +59,9 @@ static_assert(sizeof(DevElem) == 80, "DevElem layout");
 //   KQUAD      7: kq[4] dl[3]
 //   CSBEND    23: kA[4] kB[4] cph[3] sph[3] vers[3] rs[3] dl[3]
 // Scalars: EDRIFT p0 = L; MULT p0 = KnL/n!; RFCA p0 = k/2, p1 = sin(phase),
-//   p2 = cos(phase), p3 = V; RADKICK p0 = sigma; WAKE ip = nbins.
-// Pass-varying constants vc[slot] = (a, b): RFCA (P_in, 1/P_out), WAKE (kfac, 0).
+//   p2 = cos(phase), p3 = V; RADKICK p0 = sigma; WAKE, TRWAKE ip = nbins.
+// Pass-varying constants vc[slot] = (a, b): RFCA (P_in, 1/P_out), WAKE and
+// TRWAKE (kfac, 0).
 
 struct RunArgs {
   double *z[6];
@@ -76,10 +78,13 @@ struct RunArgs {
   uint32_t feat;            // element families present (selects the instantiation)
   int32_t longit;           // run reads/writes only s and delta, no apertures
   int32_t chk_lost;         // slots below *n_alive may hold lost particles (lazy compaction)
+  uint32_t *lost_flag;      // [ceil(n_total/64)]: nonzero when a particle of those 64 slots
+                            // was lost since the flags were cleared (gates the lost_at read)
   int32_t ppt;              // particles per thread (1, 2, 4, 8)
+  int32_t nt;               // light runs: non-temporal coordinate loads and stores
   int32_t grid_cap;         // grid-stride cap
   int64_t n_total;          // array length (bound of speculative loads)
-  const double *wake_v;     // V[nbins] when elements[e0] is a WAKE
+  const double *wake_v;     // V[nbins] when elements[e0] is a WAKE; Vx, Vy for a TRWAKE
   const double *wake_par;   // (smin, 1/delta)
   double *mm_part;          // [gridDim.x][2] (min s, max s) of survivors, or null
   uint32_t *zero_buf;       // zeroed by block 0 when non-null
@@ -114,10 +119,12 @@ hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_of
 // ---------------------------------------------------------------- workspace
 struct Workspace {
   double *mm_part;     // [kMaxGridStride][2]
-  uint32_t *counts;    // [TRK_MAX_BINS]
+  uint32_t *counts;    // [TRK_MAX_BINS + 64], then the dipole sums:
+  int64_t *dip;        // [2][TRK_MAX_TRBINS] (same allocation, zeroed with the counts)
+  uint32_t *lost_flag; // [ceil(n/64)] loss flags of 64-slot groups
   double *range;       // [2]
   double *wake_par;    // [2]
-  double *wake_v;      // [TRK_MAX_BINS]
+  double *wake_v;      // [2 * TRK_MAX_BINS]
   double *mom_shift;   // [6]
   double *mom_tmp;     // [28]
   double *mom_part;    // [kMaxPassesPerLaunch][nblk][28]
@@ -139,9 +146,17 @@ inline int64_t nblocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
 hipError_t launch_run(const RunArgs &a, int grid, hipStream_t st);
 hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_total, double *mm_part,
                          int grid, uint32_t *zero_buf, int zero_n, hipStream_t st);
+// x, y, dip non-null: also the dipole sums dip[2][nbins] (zeroed beforehand)
 hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_total,
                             const double *mm_part, int mm_n, int nbins, uint32_t *counts,
-                            double *range, hipStream_t st);
+                            double *range, hipStream_t st, const double *x = nullptr,
+                            const double *y = nullptr, int64_t *dip = nullptr);
+// transverse: v[2][nbins] from dip[2][nbins]
+hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range, double tau0,
+                              double omega, int mode, double *v, double *wake_par, hipStream_t st);
+hipError_t launch_trwake_kick(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                              const double *v, const double *wake_par, int nbins, double kfac,
+                              hipStream_t st);
 // v: the convolution; wake_par: (smin, nbins/width) or null
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
                            double omega, int mode, double *v, double *wake_par, hipStream_t st);

@@ -70,3 +70,20 @@ def test_surrogate_host_checks_without_gpu():
                              None) == binding.TRK_EINVAL
     info = binding.SurrInfo()
     assert lib.trk_surrogate_get_info(None, C.byref(info)) == binding.TRK_EINVAL
+
+
+def test_transverse_wake_host_checks_without_gpu():
+    from paper_1710_07350_amd.inputs import Element
+    import pytest
+    lib = binding.lib()
+    for nb in (1, 2049):
+        with pytest.raises(binding.TrkError) as e:
+            binding.Lattice([Element("TRWAKE", nbins=nb, wake_tau0=1e-11)])
+        assert e.value.status == binding.TRK_EINVAL
+    with pytest.raises(binding.TrkError):
+        binding.Lattice([Element("TRWAKE", nbins=64, wake_tau0=0.0)])
+    # bin counts beyond the transverse limit are rejected before any device call
+    assert lib.trk_dipole_histogram(None, 4096, None, None, None, None, 0, None) == \
+        binding.TRK_ERANGE
+    assert lib.trk_trwake_convolve(None, 1, None, 1e-11, 0.0, 0, None, None) == binding.TRK_ERANGE
+    assert lib.trk_trwake_convolve(None, 64, None, 1e-11, 0.0, 7, None, None) == binding.TRK_EINVAL

@@ -40,8 +40,13 @@ def test_fodo_parity_with_moments(torch):
 
 
 @pytest.mark.parametrize("kw", [dict(passes_per_launch=1), dict(passes_per_launch=7),
-                                dict(max_elems_per_launch=5), dict(max_elems_per_launch=1)])
+                                dict(max_elems_per_launch=5), dict(max_elems_per_launch=1),
+                                dict(max_elems_per_launch=1, run_nt=1),
+                                dict(max_elems_per_launch=2, run_nt=1, run_ppt=4, run_blocks=3),
+                                dict(max_elems_per_launch=3, run_nt=-1, run_ppt=8)])
 def test_fodo_fusion_depth_does_not_change_results(torch, kw):
+    """Fusion depth, streaming stores and launch shape change traffic, never
+    results; with losses in early runs, later runs skip the lost slots."""
     lat = inputs.fodo_lattice()
     d = inputs.gaussian_beam(3000, seed=4, sigmas=WIDE)
     r = run_oracle(lat, d, 12)
@@ -297,6 +302,30 @@ def test_host_pointer_rejected(torch):
 
 
 # ------------------------------------------------------------------ full-size, sampled
+@pytest.mark.parametrize("fusion", [1, 3])
+def test_fodo_1e7_streaming_sampled(torch, fusion):
+    """1e7 particles of the FODO channel with short runs, the launch shape of
+    the bandwidth measurement (coordinates beyond the Infinity Cache, so the
+    runs stream with non-temporal accesses), 2 passes; 600 sampled particles
+    re-tracked alone by the oracle."""
+    lat = inputs.fodo_lattice()
+    n = 10_000_000
+    d = inputs.gaussian_beam(n, seed=0, sigmas=WIDE)
+    g = run_gpu(lat, d, 2, max_elems_per_launch=fusion)
+    assert 0 < g["n_alive"] < n
+    rng = np.random.default_rng(fusion)
+    pick = np.sort(rng.choice(n, 600, replace=False))
+    sub = {"z": d["z"][:, pick].copy(), "id": d["id"][pick].copy(), "lost_at": d["lost_at"][pick].copy()}
+    r = run_oracle(lat, sub, 2)
+    where = np.empty(n, dtype=np.int64)
+    where[g["id"]] = np.arange(n)
+    rows = where[r["id"]]
+    assert np.array_equal(g["lost_at"][rows], r["lost_at"])
+    assert np.array_equal(g["z"][:, rows], r["z"])
+    assert (g["lost_at"][: g["n_alive"]] < 0).all()
+    assert (g["lost_at"][g["n_alive"]:] >= 0).all()
+
+
 def test_ring_full_size_sampled(torch):
     """1e6 particles of the storage-ring workload, as tracked by the bench,
     for 10 turns; 600 sampled particles re-tracked alone by the oracle

@@ -1,0 +1,165 @@
+"""Parity of the transverse wake (TRWAKE) on the GPU with the CPU oracle:
+the dipole sums are exact integers and match bit for bit, the binary64
+convolution and the kick are bit-exact, the FP32 matrix-core convolution
+stays inside its rounding bound, and tracking a lattice with transverse
+wakes reproduces the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_07350_amd import binding as B
+from paper_1710_07350_amd import inputs
+from paper_1710_07350_amd.inputs import Element
+
+from helpers import assert_bit_exact, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TAU0, OMEGA = 10e-12, 2 * math.pi * 50e9
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def offset_beam(n, seed, dx=2e-4, dy=-1e-4):
+    d = inputs.gaussian_beam(n, seed=seed)
+    d["z"][0] += dx
+    d["z"][2] += dy
+    return d
+
+
+@pytest.mark.parametrize("n,nb", [(1, 8), (1000, 7), (123457, 1024), (300000, 2048), (5000, 2)])
+def test_dipole_histogram_bit_exact(torch, n, nb):
+    d = offset_beam(n, n)
+    if n > 100:
+        d["z"][0][::97] = 1.5          # clamped to 1 m
+        d["z"][2][::89] = np.nan       # counts 0
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    rg, cnt, dip = B.dipole_histogram(beam, nb, ws)
+    rr, rc, rx, ry = oracle.dipole_histogram(d["z"][4], d["z"][0], d["z"][2], d["lost_at"], nb)
+    assert np.array_equal(rg.cpu().numpy(), rr)
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint32), rc)
+    dip = dip.cpu().numpy()
+    assert np.array_equal(dip[0], rx) and np.array_equal(dip[1], ry)
+
+
+def test_dipole_histogram_nobody_alive(torch):
+    d = offset_beam(500, 1)
+    beam = B.Beam(d["z"], d["id"], d["lost_at"], n_alive=0)
+    ws = B.Workspace(beam.n)
+    rg, cnt, dip = B.dipole_histogram(beam, 64, ws)
+    assert rg.cpu().numpy().tolist() == [0.0, 0.0] and int(cnt.sum()) == 0
+    assert not dip.cpu().numpy().any()
+
+
+@pytest.mark.parametrize("nb", [2, 17, 1024, 2048])
+def test_trwake_convolution(torch, nb):
+    rng = np.random.default_rng(nb)
+    dip = rng.integers(-2 ** 45, 2 ** 45, (2, nb)).astype(np.int64)
+    rg = np.array([-2e-3, 3e-3])
+    w = oracle.trwake_table(rg[0], rg[1], nb, TAU0, OMEGA)
+    dm = [oracle.dipole_metres(dip[p]) for p in (0, 1)]
+    ref = np.stack([oracle.convolve_f64(dm[p], w) for p in (0, 1)])
+    dt = torch.tensor(dip, device="cuda")
+    rt = torch.tensor(rg, device="cuda")
+    v64 = B.trwake_convolve(dt, nb, rt, TAU0, OMEGA, B.WAKE_FP64).cpu().numpy()
+    assert np.array_equal(v64, ref)
+    v32 = B.trwake_convolve(dt, nb, rt, TAU0, OMEGA, B.WAKE_FP32_MFMA).cpu().numpy()
+    for p in (0, 1):
+        scale = np.convolve(np.abs(dm[p]), np.abs(w))[:nb]
+        # FP32 products and sums over at most nb terms, plus the rounding of
+        # the weights and of the table to binary32
+        assert np.all(np.abs(v32[p] - ref[p]) <= (nb + 3) * 2.0 ** -24 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("n", [1, 2049, 200_000])
+def test_trwake_kick_call_bit_exact(torch, n):
+    d = offset_beam(n, 3)
+    nb, A, Q, P = 256, 1e16, 1e-9, 2e8
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    rg, cnt, dip = B.dipole_histogram(beam, nb, ws)
+    B.trwake_kick(beam, dip, nb, rg, A, TAU0, OMEGA, Q, P, B.WAKE_FP64, ws)
+    torch.cuda.synchronize()
+    g = beam.host()
+    rr, rc, rx, ry = oracle.dipole_histogram(d["z"][4], d["z"][0], d["z"][2], d["lost_at"], nb)
+    w = oracle.trwake_table(rr[0], rr[1], nb, TAU0, OMEGA)
+    vx = oracle.convolve_f64(oracle.dipole_metres(rx), w)
+    vy = oracle.convolve_f64(oracle.dipole_metres(ry), w)
+    b = oracle.Beam.from_inputs(d)
+    oracle.trwake_kick(b, rr, vx, vy, ((Q / n) * A) / P)
+    assert np.array_equal(g["z"], b.z)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(max_elems_per_launch=1), dict(run_longit=-1)])
+def test_rfcw_lattice_fp64_bit_exact(torch, kw):
+    """The bunch compressor with a transverse wake after each cavity's
+    longitudinal one, binary64 wakes: bit-exact with the oracle."""
+    lat = inputs.rfcw_lattice(nbins=512)
+    d = inputs.gaussian_beam(60_000, seed=5, chirp=inputs.BC_CHIRP)
+    d["z"][0] += 1e-4
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, **kw)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+    assert np.abs(r["z"][1] - d["z"][1]).max() > 1e-9       # the transverse wake acts
+
+
+def test_trwake_after_losses(torch):
+    """Apertures lose particles before a transverse wake within one call:
+    the lazily compacted beam is packed before the dipole histogram."""
+    a = dict(aperture="RECT", ax=1.5e-3, ay=1.5e-3)
+    lat = [Element("EDRIFT", L=2.0, **a), Element("QUAD", L=0.2, k=1.2, **a),
+           Element("TRWAKE", wake_A=3e16, wake_tau0=TAU0, wake_omega=OMEGA, charge=1e-9, nbins=128),
+           Element("EDRIFT", L=1.0, **a),
+           Element("TRWAKE", wake_A=3e16, wake_tau0=TAU0, wake_omega=OMEGA, charge=1e-9, nbins=64)]
+    d = inputs.gaussian_beam(20_000, seed=9, sigmas=(2e-3, 2e-4, 2e-3, 2e-4, 1e-3, 1e-3))
+    for kw in (dict(), dict(max_elems_per_launch=1)):
+        g = run_gpu(lat, d, 3, wake_mode=B.WAKE_FP64, **kw)
+        r = run_oracle(lat, d, 3)
+        assert 0 < r["n_alive"] < 20_000
+        assert_bit_exact(g, r)
+
+
+def test_rfcw_fp32_mfma_within_bound(torch):
+    """FP32 matrix-core wakes: losses, ids and x, y are identical; the slopes
+    stay within the bound of the FP32 convolutions.  x, y and s do not move
+    before the chicane, so every transverse wake sees the dipole sums of the
+    initial beam; each V errs by at most (nbins + 3) 2^-24 sum_j |D_j W[i-j]|
+    and the kick passes that on scaled by kfac / pz."""
+    lat = inputs.rfcw_lattice()
+    n = 400_000
+    d = inputs.gaussian_beam(n, seed=6, chirp=inputs.BC_CHIRP)
+    d["z"][0] += 1e-4
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert g["n_alive"] == r["n_alive"] == n
+    assert np.array_equal(g["id"], r["id"])
+    assert np.array_equal(g["z"][0], r["z"][0]) and np.array_equal(g["z"][2], r["z"][2])
+    tw = [e for e in lat if e.kind == "TRWAKE"][0]
+    nb = tw.nbins
+    rr, rc, rx, ry = oracle.dipole_histogram(d["z"][4], d["z"][0], d["z"][2], d["lost_at"], nb)
+    w = np.abs(oracle.trwake_table(rr[0], rr[1], nb, tw.wake_tau0, tw.wake_omega))
+    bound_v = [(nb + 3) * 2.0 ** -24 * np.convolve(np.abs(oracle.dipole_metres(q)), w)[:nb].max()
+               for q in (rx, ry)]
+    P, kf = inputs.BC_P0_EV, 0.0
+    for e in lat:
+        if e.kind == "RFCA":
+            P = P + e.volt * math.cos(e.phase)
+        if e.kind == "TRWAKE":
+            kf += ((e.charge / n) * e.wake_A) / P
+    pz_min = 1.0 + min(r["z"][5].min(), d["z"][5].min()) - 1e-3
+    for k, bv in ((1, bound_v[0]), (3, bound_v[1])):
+        err = np.abs(g["z"][k] - r["z"][k]).max()
+        bd = kf * bv / pz_min * 1.001 + 1e-18
+        assert err <= bd, (k, err, bd)
+    kick = np.abs(r["z"][1] - d["z"][1]).max()
+    assert kick > 1e-9
+    print(f"FP32 transverse wake: max |d x'| = {np.abs(g['z'][1] - r['z'][1]).max():.3e} "
+          f"of a max kick {kick:.3e}")
