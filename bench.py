@@ -33,12 +33,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WAKES = ("WAKE", "TRWAKE")
 # HBM bytes of the dominant kernel per launch, keyed by (workload, element
 # limit per launch), from rocprofv3 FETCH_SIZE and WRITE_SIZE (FETCH_SIZE
 # scaled by 2.000, WRITE_SIZE by 1.000, the factors a 1 GiB copy gives),
 # averaged over the runs of one pass (profiles/*_hbm_bytes.md); absent until
 # measured for the current kernel.
-TRAFFIC_PER_LAUNCH = {("bc", 0): 99795195, ("roof", 1): 734042624}
+TRAFFIC_PER_LAUNCH = {("roof", 1): 734042624}
 # FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
 # particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="bc",
-                    choices=["bc", "ring", "fodo", "roof", "surr", "batch"])
+                    choices=["bc", "rfcw", "ring", "fodo", "roof", "surr", "batch", "compact"])
     ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--precision", default="bf16x2", choices=["bf16", "bf16x2"])
     ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
@@ -98,6 +99,8 @@ def run_mask_bytes(lattice, e0, e1, moments=False, next_wake=False):
             rd |= set(range(6)); wr |= {0, 1, 2, 3, 4}
         elif k in ("RFCA", "WAKE"):
             rd |= {4, 5}; wr |= {5}
+        elif k == "TRWAKE":
+            rd |= {1, 3, 4, 5}; wr |= {1, 3}
         elif k == "RADKICK":
             rd |= {5}; wr |= {5}; need_id = True
         if e.aperture != "NONE":
@@ -113,14 +116,14 @@ def run_mask_bytes(lattice, e0, e1, moments=False, next_wake=False):
 def launches_of(lattice, passes_per_launch=16, max_e=0):
     """(e0, e1, npass) of each fused launch, as the library plans them."""
     n = len(lattice)
-    has_wake = any(e.kind == "WAKE" for e in lattice)
+    has_wake = any(e.kind in WAKES for e in lattice)
     if not has_wake and (max_e == 0 or max_e >= n):
         return [(0, n, passes_per_launch)]
     out, e0 = [], 0
     lim = max_e if max_e > 0 else n
     while e0 < n:
         e1 = e0 + 1
-        while e1 < n and lattice[e1].kind != "WAKE" and e1 - e0 < lim:
+        while e1 < n and lattice[e1].kind not in WAKES and e1 - e0 < lim:
             e1 += 1
         out.append((e0, e1, 1))
         e0 = e1
@@ -412,6 +415,61 @@ def batch_bench(args):
     print(json.dumps(out))
 
 
+def compact_bench(args):
+    """The paper's comparison of loss reorderings (Sec. 2.5): time the stable
+    reordering, the paper's sparse swap and the sort by key on 4e6 particles
+    with 0.5, 5, 10 and 50 % of them lost at random slots."""
+    import torch
+    from paper_1710_07350_amd import binding as B
+    from paper_1710_07350_amd import inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = int(args.particles or 4_000_000)
+    reps = args.steps or 10
+    d = inputs.gaussian_beam(n, seed=0)
+    tmpl = B.Beam.from_inputs(d)
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(n)
+    stream = torch.cuda.current_stream()
+    modes = {"stable": B.COMPACT_STABLE, "swap": B.COMPACT_SWAP, "sort": B.COMPACT_SORT}
+    rng = np.random.default_rng(1)
+    rows = []
+    for frac in (0.005, 0.05, 0.1, 0.5):
+        la = np.full(n, -1, np.int64)
+        sel = rng.random(n) < frac
+        la[sel] = (rng.integers(0, 9, sel.sum()) << 32) | rng.integers(0, 401, sel.sum())
+        lost_t = torch.tensor(la, device="cuda")
+        for name, mode in modes.items():
+            times = []
+            for r in range(reps + 1):
+                beam.z.copy_(tmpl.z)
+                beam.id.copy_(tmpl.id)
+                beam.lost_at.copy_(lost_t)
+                beam.n_alive.fill_(n)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                B.compact_lost(beam, ws, stream=stream, mode=mode)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r > 0:
+                    times.append(e0.elapsed_time(e1))
+            assert int(beam.n_alive.item()) == n - int(sel.sum())
+            rows.append({"lost_fraction": frac, "mode": name, "ms": float(np.median(times))})
+    ms = {(r["lost_fraction"], r["mode"]): r["ms"] for r in rows}
+    ratios = {f"{f:g}": {"sort/swap": ms[(f, "sort")] / ms[(f, "swap")],
+                         "stable/swap": ms[(f, "stable")] / ms[(f, "swap")]}
+              for f in (0.005, 0.05, 0.1, 0.5)}
+    out = {"metric": "loss reordering time per call (ms), stable reordering at 5 % loss",
+           "value": ms[(0.05, "stable")], "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1,
+           "ms_per_step": ms[(0.05, "stable")], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"loss reordering of {n:.0e} particles with losses at random "
+                                  "slots (stable, the paper's sparse swap, sort by key)",
+                      "particles": n},
+           "table": rows, "ratios": ratios, "roofline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -422,6 +480,8 @@ def main():
         return surrogate_bench(args)
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "compact":
+        return compact_bench(args)
     import torch
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs
@@ -431,8 +491,8 @@ def main():
     wl = args.workload
     wake_mode = B.WAKE_FP32_MFMA if args.wake_mode == "fp32" else B.WAKE_FP64
 
-    if wl == "bc":
-        lat = inputs.bc_lattice()
+    if wl in ("bc", "rfcw"):
+        lat = inputs.bc_lattice() if wl == "bc" else inputs.rfcw_lattice()
         n = int(args.particles or 4_000_000)
         beam_kw = dict(n=n, seed=0, chirp=inputs.BC_CHIRP)
         p_ref, passes_per_step = inputs.BC_P0_EV, 1
@@ -440,7 +500,11 @@ def main():
         warm = args.warmup if args.warmup is not None else 5
         fresh = True
         cfg = {"workload": "linac bunch compressor: 4e6-particle chirped Gaussian beam, "
-                           "8 x (RF cavity + 1024-bin wake step) + 2nd-order chicane",
+                           "8 x (RF cavity + 1024-bin wake step) + 2nd-order chicane"
+                           if wl == "bc" else
+                           "linac bunch compressor with transverse wakes: 4e6-particle chirped "
+                           "Gaussian beam, 8 x (RF cavity + 1024-bin longitudinal and transverse "
+                           "wake steps) + 2nd-order chicane",
                "particles": n, "elements_per_pass": len(lat),
                "wake_convolution": "fp32-mfma" if wake_mode == B.WAKE_FP32_MFMA else "fp64",
                "batch": "fresh device-resident beam per step"}
@@ -480,7 +544,11 @@ def main():
     d = inputs.gaussian_beam(**beam_kw)
     template = B.Beam.from_inputs(d)
     ws = B.Workspace(n)
-    nb = (warm + steps) if fresh else 1
+    # two timed regions of `steps` steps each: the first, without per-kernel
+    # events (an event between two kernels stalls the queue for a few us), gives
+    # the throughput; the second, with HIP events around every fused run on the
+    # same stream, gives the run kernel's average duration for the roofline
+    nb = (warm + 2 * steps) if fresh else 1
     beams = []
     for _ in range(nb):
         b = B.Beam.__new__(B.Beam)
@@ -501,45 +569,51 @@ def main():
                 moments=mom if use_mom else None, wake_mode=wake_mode,
                 max_elems_per_launch=args.fusion, stream=stream)
 
+    def timed(i0, i1):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for i in range(i0, i1):
+            one_step(i)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
     for i in range(warm):
         one_step(i)
     torch.cuda.synchronize()
+    ms_total = timed(warm, warm + steps)
     B.profile_enable(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    for i in range(warm, warm + steps):
-        one_step(i)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = t0.elapsed_time(t1)
+    timed(warm + steps, warm + 2 * steps)
     run_ms, run_launches = B.profile_read(0)
     B.profile_enable(False)
 
-    # exact particle-element steps of the timed region
-    if fresh:
-        total_steps = 0.0
-        for i in range(warm, warm + steps):
-            la = beams[i].lost_at.cpu().numpy()
-            total_steps += element_steps(lat, passes_per_step, n, la, 0)
-    else:
+    def steps_of(i0, i1):
+        """exact particle-element steps of steps [i0, i1)"""
+        if fresh:
+            tot = 0.0
+            for i in range(i0, i1):
+                la = beams[i].lost_at.cpu().numpy()
+                tot += element_steps(lat, passes_per_step, n, la, 0)
+            return tot
         # a continuing beam: count survivors per turn from the loss records
         la = beams[0].lost_at.cpu().numpy()
-        first = warm * passes_per_step
-        last = (warm + steps) * passes_per_step
+        first = i0 * passes_per_step
+        last = i1 * passes_per_step
         nel = len(lat)
         lp = la >> 32
-        total_steps = 0.0
-        alive_end = float((la < 0).sum())
         lost = la >= 0
-        after = lost & (lp >= last)
-        total_steps += (alive_end + float(after.sum())) * (last - first) * nel
+        alive_then = float((la < 0).sum()) + float((lost & (lp >= last)).sum())
+        tot = alive_then * (last - first) * nel
         inside = lost & (lp >= first) & (lp < last)
         pl = lp[inside] - first
         el = la[inside] & 0xFFFFFFFF
-        total_steps += float((pl * nel + el + 1).sum())
+        return tot + float((pl * nel + el + 1).sum())
+
+    total_steps = steps_of(warm, warm + steps)
     value = total_steps / (ms_total / 1e3)
+    prof_steps = steps_of(warm + steps, warm + 2 * steps)
 
     # roofline of the dominant kernel (fused element run)
     plan = launches_of(lat, 16, args.fusion)
@@ -547,7 +621,7 @@ def main():
     launches_per_pass = 0.0
     for j, (e0, e1, npass) in enumerate(plan):
         nxt = plan[(j + 1) % len(plan)][0] if len(plan) > 1 else None
-        next_wake = nxt is not None and lat[nxt].kind == "WAKE" and (j + 1 < len(plan))
+        next_wake = nxt is not None and lat[nxt].kind in WAKES and (j + 1 < len(plan))
         per = run_mask_bytes(lat, e0, e1, moments=(use_mom and e1 == len(lat)),
                              next_wake=next_wake)
         if npass > 1:
@@ -556,7 +630,7 @@ def main():
         else:
             bytes_per_pass += per
             launches_per_pass += 1.0
-    alive_mean = total_steps / (steps * passes_per_step * len(lat))
+    alive_mean = prof_steps / (steps * passes_per_step * len(lat))
     alg_bytes_per_launch = alive_mean * bytes_per_pass / launches_per_pass
     avg_ms = run_ms / max(run_launches, 1)
     achieved = alg_bytes_per_launch / (avg_ms / 1e3) / 1e9
@@ -570,7 +644,7 @@ def main():
     # the FP64 vector units: report it against their peak instead
     fpp = FP64_FLOP_PER_STEP.get("fodo" if wl in ("fodo", "roof") else wl)
     if fpp is not None:
-        steps_per_launch = total_steps / max(run_launches, 1)
+        steps_per_launch = prof_steps / max(run_launches, 1)
         flops = fpp * steps_per_launch
         if flops / max(alg_bytes_per_launch, 1.0) > FP64_PEAK_TFLOPS / (HBM_PEAK_GBS / 1e3):
             ach = flops / (avg_ms / 1e3) / 1e12

@@ -228,6 +228,21 @@ int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t w
  * rank of (pass, element), scatter), so the host never waits. */
 int trk_compact_lost(trk_beam *beam, void *workspace, size_t workspace_bytes, void *stream);
 
+/* The paper's two loss reorderings (Sec. 2.5), for comparison with the
+ * stable one above; both act on [0, *n_alive) like it and decrease *n_alive.
+ *   TRK_COMPACT_STABLE  trk_compact_lost.
+ *   TRK_COMPACT_SWAP    the sparse algorithm: the k-th lost particle of the
+ *                       head [0, n_new) swaps with the k-th survivor of the
+ *                       tail [n_new, n_old) (index order); nothing else
+ *                       moves.  Survivors do not keep their order.
+ *   TRK_COMPACT_SORT    sort by key: a device radix sort of key = i
+ *                       (survivor) or i + N (lost); survivors, then the lost
+ *                       particles, each in their previous order.
+ * n_total must be below 2^31.  The result of each mode is deterministic. */
+enum trk_compact_mode { TRK_COMPACT_STABLE = 0, TRK_COMPACT_SWAP = 1, TRK_COMPACT_SORT = 2 };
+int trk_compact_lost_mode(trk_beam *beam, int32_t mode, void *workspace, size_t workspace_bytes,
+                          void *stream);
+
 /* ------------------------------------------------------------------ batches
  * Many variants of one lattice structure (same element kinds in the same
  * order; strengths, apertures and seeds may differ), each with its own beam

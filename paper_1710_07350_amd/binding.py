@@ -26,7 +26,7 @@ MAX_BINS = 4096
 EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
            "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_dipole_histogram",
            "trk_trwake_convolve", "trk_trwake_kick", "trk_moments",
-           "trk_compact_lost", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
+           "trk_compact_lost", "trk_compact_lost_mode", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
            "trk_batch_create", "trk_batch_destroy", "trk_batch_workspace_size",
            "trk_track_batched", "trk_mlp_create", "trk_mlp_destroy", "trk_mlp_get_params",
@@ -128,6 +128,7 @@ def lib():
                                     vp, sz, vp]
         L.trk_moments.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
         L.trk_compact_lost.argtypes = [C.POINTER(BeamStruct), vp, sz, vp]
+        L.trk_compact_lost_mode.argtypes = [C.POINTER(BeamStruct), i32, vp, sz, vp]
         L.trk_elementary.argtypes = [i32, vp, vp, vp, i64, vp]
         L.trk_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
         L.trk_gauss.argtypes = [vp, u32, u32, u64, vp, i64, vp]
@@ -382,9 +383,16 @@ def moments(beam: Beam, ws: Workspace, stream=None):
     return out
 
 
-def compact_lost(beam: Beam, ws: Workspace, stream=None) -> None:
-    _check(lib().trk_compact_lost(C.byref(beam.struct()), ws.ptr, ws.nbytes,
-                                  _stream_handle(stream)))
+COMPACT_STABLE, COMPACT_SWAP, COMPACT_SORT = 0, 1, 2
+
+
+def compact_lost(beam: Beam, ws: Workspace, stream=None, mode: int = COMPACT_STABLE) -> None:
+    if mode == COMPACT_STABLE:
+        _check(lib().trk_compact_lost(C.byref(beam.struct()), ws.ptr, ws.nbytes,
+                                      _stream_handle(stream)))
+    else:
+        _check(lib().trk_compact_lost_mode(C.byref(beam.struct()), mode, ws.ptr, ws.nbytes,
+                                           _stream_handle(stream)))
 
 
 def elementary(fn: int, x, y=None, stream=None):

@@ -487,6 +487,9 @@ Workspace carve(void *base, int64_t n_total, size_t *bytes) {
   w.mom_tmp = c.take<double>(28);
   w.mom_part = c.take<double>(static_cast<size_t>(kMomPassesMax) * std::max<size_t>(nb, 1024) * 28);
   w.cmp_blk = c.take<int64_t>(nb * 10);
+  const size_t ct = static_cast<size_t>(std::max<int64_t>(compact_tiles(n_total), 1));
+  w.rs_cnt = c.take<uint32_t>(256 * ct);
+  w.rs_tot = c.take<uint32_t>(256);
   w.cmp_hdr = c.take<int64_t>(16);
   w.key_a = c.take<uint64_t>(n);
   w.key_b = c.take<uint64_t>(n);
@@ -495,6 +498,8 @@ Workspace carve(void *base, int64_t n_total, size_t *bytes) {
   for (int k = 0; k < 6; ++k) w.tz[k] = c.take<double>(n);
   w.tid = c.take<uint32_t>(n);
   w.tlost = c.take<int64_t>(n);
+  w.sort_tmp_bytes = sortkey_temp_bytes(static_cast<int64_t>(n));
+  w.sort_tmp = c.take<char>(w.sort_tmp_bytes);
   if (bytes) *bytes = c.off + 256;
   return w;
 }
@@ -896,6 +901,26 @@ extern "C" int trk_moments(const trk_beam *beam, double *out_dev, void *workspac
   HIP_TRY(launch_mom_partial(z, beam->n_alive, beam->n_total, w.mom_shift, w.mom_part, g, st),
           "moments");
   HIP_TRY(launch_mom_finalize(w.mom_part, g, 1, w.mom_shift, out_dev, 28, nullptr, st), "moments");
+  return TRK_OK;
+}
+
+extern "C" int trk_compact_lost_mode(trk_beam *beam, int32_t mode, void *workspace,
+                                     size_t workspace_bytes_, void *stream) {
+  if (mode != TRK_COMPACT_STABLE && mode != TRK_COMPACT_SWAP && mode != TRK_COMPACT_SORT)
+    return fail(TRK_EINVAL, "unknown compaction mode");
+  if (mode == TRK_COMPACT_STABLE)
+    return trk_compact_lost(beam, workspace, workspace_bytes_, stream);
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  if (beam->n_total == 0) return TRK_OK;
+  if (beam->n_total > 0x7fffffffLL) return fail(TRK_ERANGE, "n_total beyond 2^31 - 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  double *z[6];
+  beam_ptrs(beam, z);
+  HIP_TRY(launch_compact_variant(mode, z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w,
+                                 st),
+          "compact");
   return TRK_OK;
 }
 

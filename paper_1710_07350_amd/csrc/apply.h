@@ -93,4 +93,39 @@ __device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const El
   }
 }
 
+// Runs that touch only s and delta (RF cavities, wake kicks, maps whose other
+// rows are identities, markers; no apertures): the arithmetic of apply() on
+// the two coordinates, without the registers of the other element kinds.
+template <uint32_t kFeat>
+__device__ __forceinline__ void apply_long(const DevElem &E, ConstPool pool, const ElemCtx &cx,
+                                           int p, double &s, double &d) {
+  switch (E.kind) {
+    case K_MAP2_P2: {
+      ConstPool c = pool + E.off;
+      double a = c[4] * s;
+      a = fma(c[5], d, a);
+      a = fma(c[7], d * d, a);
+      s = a;
+      d = c[6] * d;
+      break;
+    }
+    case K_RFCA:
+      if constexpr ((kFeat & F_RF) != 0) {
+        const int v = p * cx.nv + (E.vslot - cx.v0);
+        double z[6] = {0.0, 0.0, 0.0, 0.0, s, d};
+        el::rfca(z, E.p0, E.p1, E.p2, E.p3, cx.vc[v][0], cx.vc[v][1]);
+        d = z[5];
+      }
+      break;
+    case K_WAKE:
+      if constexpr ((kFeat & F_WAKE) != 0) {
+        const int v = p * cx.nv + (E.vslot - cx.v0);
+        const double vs = el::wake_interp(s, cx.wake_par[0], cx.wake_par[1], cx.wake_v, E.ip);
+        d = fma(-cx.vc[v][0], vs, d);
+      }
+      break;
+    default: break;
+  }
+}
+
 }  // namespace trk

@@ -91,8 +91,13 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       for (int e = a.e0; e < a.e1; ++e) {
         const DevElem E = elems[e];
 #pragma unroll
-        for (int q = 0; q < kP; ++q)
-          apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
+        for (int q = 0; q < kP; ++q) {
+          if constexpr (kLong) {
+            if (alive[q]) apply_long<kFeat>(E, pool, cx, p, z[q][4], z[q][5]);
+          } else {
+            apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
+          }
+        }
       }
       if constexpr (kMom) {
         double *row = a.mom_part + (static_cast<int64_t>(p) * gridDim.x + blockIdx.x) * 28;

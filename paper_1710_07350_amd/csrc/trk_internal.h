@@ -135,6 +135,10 @@ struct Workspace {
   double *tz[6];       // [n] scatter staging
   uint32_t *tid;       // [n]
   int64_t *tlost;      // [n]
+  uint32_t *rs_cnt;    // [256][compaction tiles] digit counts of the multi-block sort
+  uint32_t *rs_tot;    // [256]
+  void *sort_tmp;      // device radix-sort scratch of the sort-by-key compaction
+  size_t sort_tmp_bytes;
 };
 size_t workspace_bytes(int64_t n_total);
 Workspace carve_workspace(void *base, int64_t n_total);
@@ -172,6 +176,12 @@ hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const d
                                double *out, int out_stride, double *mean_out, hipStream_t st);
 hipError_t launch_compact(double *const z[6], uint32_t *id, int64_t *lost_at, int64_t *n_alive,
                           int64_t n_total, const Workspace &w, hipStream_t st);
+// the paper's sparse swap (TRK_COMPACT_SWAP) or sort by key (TRK_COMPACT_SORT)
+hipError_t launch_compact_variant(int mode, double *const z[6], uint32_t *id, int64_t *lost_at,
+                                  int64_t *n_alive, int64_t n_total, const Workspace &w,
+                                  hipStream_t st);
+size_t sortkey_temp_bytes(int64_t n_total);
+int64_t compact_tiles(int64_t n_total);  // 4096-slot tiles of the compaction kernels
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
 hipError_t launch_elementary(int fn, const double *x, const double *y, double *out, int64_t n,
                              hipStream_t st);

@@ -87,3 +87,8 @@ def test_transverse_wake_host_checks_without_gpu():
         binding.TRK_ERANGE
     assert lib.trk_trwake_convolve(None, 1, None, 1e-11, 0.0, 0, None, None) == binding.TRK_ERANGE
     assert lib.trk_trwake_convolve(None, 64, None, 1e-11, 0.0, 7, None, None) == binding.TRK_EINVAL
+
+
+def test_compaction_mode_checked_without_gpu():
+    lib = binding.lib()
+    assert lib.trk_compact_lost_mode(None, 9, None, 0, None) == binding.TRK_EINVAL

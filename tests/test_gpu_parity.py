@@ -270,6 +270,34 @@ def test_compaction_order(torch, frac):
     assert np.array_equal(g["z"], ref.z)
 
 
+@pytest.mark.parametrize("passes,elems,frac", [(1000, 60000, 0.3), (1 << 20, 4001, 0.2),
+                                               (1, 1, 0.4)])
+def test_compaction_order_wide_and_narrow_keys(torch, passes, elems, frac):
+    """Loss records spanning 26 bits of dense rank (four radix passes), 33 bits
+    (beyond the multi-block sort: one workgroup sorts), and a single record
+    value (no pass at all), each with more than 16384 lost particles."""
+    rng = np.random.default_rng(passes + elems)
+    n = 150_001
+    d = inputs.gaussian_beam(n, seed=12)
+    d["id"] = rng.permutation(n).astype(np.uint32)
+    sel = rng.random(n) < frac
+    la = np.full(n, -1, np.int64)
+    la[sel] = (rng.integers(0, passes, sel.sum()) << 32) | rng.integers(0, elems, sel.sum())
+    if passes > 1:
+        la[np.nonzero(sel)[0][:2]] = [0, ((passes - 1) << 32) | (elems - 1)]
+    d["lost_at"] = la
+    beam = B.Beam.from_inputs(d)
+    ws = B.Workspace(beam.n)
+    B.compact_lost(beam, ws)
+    g = beam.host()
+    ref = oracle.Beam.from_inputs(d)
+    nal = oracle.compact(ref)
+    assert g["n_alive"] == nal
+    assert np.array_equal(g["id"], ref.id)
+    assert np.array_equal(g["lost_at"], ref.lost_at)
+    assert np.array_equal(g["z"], ref.z)
+
+
 def test_compaction_leaves_old_lost_region(torch):
     """Particles beyond n_alive (lost earlier) are not touched."""
     n = 10_000
