@@ -20,7 +20,7 @@ from . import build as _build
 _LIB = None
 
 KIND = {"EDRIFT": 1, "QUAD": 2, "MAP2": 3, "MULT": 4, "KQUAD": 5, "CSBEND": 6,
-        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11}
+        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11, "MAP3": 12}
 APER = {"NONE": 0, "RECT": 1, "ELLIPSE": 2}
 TAG_RAD = 2
 
@@ -33,7 +33,7 @@ class OrcElem(C.Structure):
                 ("wake_A", C.c_double), ("wake_tau0", C.c_double),
                 ("wake_omega", C.c_double), ("charge", C.c_double),
                 ("sigma", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
-                ("coef", C.c_double * 168)]
+                ("coef", C.c_double * 504)]
 
 
 class OrcBeam(C.Structure):
@@ -58,6 +58,7 @@ def lib():
         L.orc_gauss.argtypes = [u32, u32, u32, u64]
         L.orc_quad_coef.argtypes = [d, d, pd]
         L.orc_yoshida.argtypes = [pd, pd]
+        L.orc_quad3_coef.argtypes = [d, d, pd]
         L.orc_track.restype = i64
         L.orc_track.argtypes = [C.POINTER(OrcBeam), C.POINTER(OrcElem), i32, i32, i32, d, u64, pd]
         L.orc_histogram.argtypes = [pd, C.POINTER(C.c_int64), i64, i32, pd, pu32]
@@ -107,6 +108,12 @@ def gauss(pid: int, step: int, tag: int, seed: int) -> float:
 def quad_coef(L: float, k1: float) -> np.ndarray:
     out = np.zeros(168)
     lib().orc_quad_coef(L, k1, _ptr(out, C.c_double))
+    return out
+
+
+def quad3_coef(L: float, k1: float) -> np.ndarray:
+    out = np.zeros(504)
+    lib().orc_quad3_coef(L, k1, _ptr(out, C.c_double))
     return out
 
 
@@ -162,7 +169,7 @@ def elements(lattice) -> "C.Array":
         r.wake_A, r.wake_tau0, r.wake_omega, r.charge = e.wake_A, e.wake_tau0, e.wake_omega, e.charge
         r.sigma, r.ax, r.ay = e.sigma, e.ax, e.ay
         if e.coef is not None:
-            for j in range(168):
+            for j in range(len(e.coef)):
                 r.coef[j] = float(e.coef[j])
     return arr
 

@@ -272,6 +272,66 @@ void orc_quad_coef(double L, double k1, double coef[168]) {
   }
 }
 
+/* index of the monomial z_j z_k z_l, j <= k <= l, among the 56 cubic ones
+ * in lexicographic order (0,0,0), (0,0,1), ..., (5,5,5) */
+static int triple_index(int j, int k, int l) {
+  int n = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b)
+      for (int c = b; c < 6; ++c) {
+        if (a == j && b == k && c == l) return n;
+        ++n;
+      }
+  return -1;
+}
+
+/* Thick quadrupole to third order in the same paraxial model (x'' = -K x,
+ * y'' = K y, K = k1/(1+delta), s' = (x'^2 + y'^2)/2): the first 168
+ * coefficients as orc_quad_coef, then U[6][56].  The model is linear in
+ * the transverse coordinates, so the cubic terms are chromatic:
+ *   U_{i,j,6,6} = (1/2) d^2 R_ij / d delta^2   (i, j in one plane),
+ *   U_{5,j,k,6} = d T_5jk / d delta,
+ * with phi = omega L and omega = sqrt(|k1|/(1+delta)), so that
+ * d phi/d delta = -phi/2 and d^2 phi/d delta^2 = 3 phi/4 at delta = 0. */
+void orc_quad3_coef(double L, double k1, double coef[504]) {
+  memset(coef, 0, 504 * sizeof(double));
+  orc_quad_coef(L, k1, coef);
+  if (k1 == 0.0) return;
+  double *U = coef + 168; /* U[i*56 + triple] */
+  double w = sqrt(fabs(k1));
+  double f = w * L;
+  double cf = cos(f), sf = sin(f), c2 = cos(2.0 * f), s2 = sin(2.0 * f);
+  double ch = cosh(f), sh = sinh(f), ch2 = cosh(2.0 * f), sh2 = sinh(2.0 * f);
+  double f2 = f * f;
+  /* focusing plane: U for [R11 R12 R21 R22] and [T511 T512 T522] */
+  double fU[4] = {-(f2 / 8.0) * cf - (3.0 * f / 8.0) * sf,
+                  ((f * cf - sf) - f2 * sf) / (8.0 * w),
+                  -(w / 8.0) * ((5.0 * f * cf + 3.0 * sf) - f2 * sf),
+                  -(f2 / 8.0) * cf - (3.0 * f / 8.0) * sf};
+  double fS[3] = {-(w / 16.0) * ((4.0 * f - s2) - 2.0 * f * c2), (f * s2) / 4.0,
+                  -(2.0 * f * c2 - s2) / (16.0 * w)};
+  /* defocusing plane */
+  double dU[4] = {(f2 / 8.0) * ch + (3.0 * f / 8.0) * sh,
+                  ((f2 * sh + f * ch) - sh) / (8.0 * w),
+                  (w / 8.0) * ((5.0 * f * ch + 3.0 * sh) + f2 * sh),
+                  (f2 / 8.0) * ch + (3.0 * f / 8.0) * sh};
+  double dS[3] = {-(w / 16.0) * ((sh2 + 2.0 * f * ch2) - 4.0 * f), -(f * sh2) / 4.0,
+                  -(2.0 * f * ch2 - sh2) / (16.0 * w)};
+  const double *xU = k1 > 0 ? fU : dU, *xS = k1 > 0 ? fS : dS;
+  const double *yU = k1 > 0 ? dU : fU, *yS = k1 > 0 ? dS : fS;
+  for (int p = 0; p < 2; ++p) {
+    int o = 2 * p;
+    const double *pu = p == 0 ? xU : yU, *ps = p == 0 ? xS : yS;
+    U[(o + 0) * 56 + triple_index(o + 0, 5, 5)] = pu[0];
+    U[(o + 0) * 56 + triple_index(o + 1, 5, 5)] = pu[1];
+    U[(o + 1) * 56 + triple_index(o + 0, 5, 5)] = pu[2];
+    U[(o + 1) * 56 + triple_index(o + 1, 5, 5)] = pu[3];
+    U[4 * 56 + triple_index(o + 0, o + 0, 5)] = ps[0];
+    U[4 * 56 + triple_index(o + 0, o + 1, 5)] = ps[1];
+    U[4 * 56 + triple_index(o + 1, o + 1, 5)] = ps[2];
+  }
+}
+
 /* ======================================================================
  * Per-particle element maps.  z = (x, xp, y, yp, s, dp).
  * ====================================================================== */
@@ -321,6 +381,52 @@ static void map2(double *z, const double *coef) {
           have = 1;
         }
       }
+    out[i] = acc;
+  }
+  memcpy(z, out, sizeof out);
+}
+
+/* Third-order map (the M3 matrix tracking of the element table): as map2,
+ * then the cubic terms U_ijkl z_j z_k z_l, (j,k,l) ascending with
+ * j <= k <= l, each monomial rounded as (z_j z_k) z_l. */
+static void map3(double *z, const double *coef) {
+  double in[6], out[6];
+  memcpy(in, z, sizeof in);
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    int have = 0;
+    if (coef[i] != 0.0) {
+      acc = coef[i];
+      have = 1;
+    }
+    for (int j = 0; j < 6; ++j) {
+      double r = coef[6 + i * 6 + j];
+      if (r != 0.0) {
+        acc = have ? fma(r, in[j], acc) : r * in[j];
+        have = 1;
+      }
+    }
+    int p = 0;
+    for (int j = 0; j < 6; ++j)
+      for (int k = j; k < 6; ++k, ++p) {
+        double tc = coef[42 + i * 21 + p];
+        if (tc != 0.0) {
+          double m = in[j] * in[k];
+          acc = have ? fma(tc, m, acc) : tc * m;
+          have = 1;
+        }
+      }
+    int q = 0;
+    for (int j = 0; j < 6; ++j)
+      for (int k = j; k < 6; ++k)
+        for (int l = k; l < 6; ++l, ++q) {
+          double u = coef[168 + i * 56 + q];
+          if (u != 0.0) {
+            double m = (in[j] * in[k]) * in[l];
+            acc = have ? fma(u, m, acc) : u * m;
+            have = 1;
+          }
+        }
     out[i] = acc;
   }
   memcpy(z, out, sizeof out);
@@ -757,10 +863,14 @@ int64_t orc_track(orc_beam *b, const orc_elem *lat, int32_t nelem, int32_t passe
   kd_const *kd = (kd_const *)calloc((size_t)(nelem > 0 ? nelem : 1), sizeof(kd_const));
   for (int32_t e = 0; e < nelem; ++e)
     if (lat[e].kind == ORC_KQUAD || lat[e].kind == ORC_CSBEND) kd_constants(&lat[e], &kd[e]);
-  double *qcoef = (double *)calloc((size_t)(nelem > 0 ? nelem : 1) * 168, sizeof(double));
+  double *qcoef = (double *)calloc((size_t)(nelem > 0 ? nelem : 1) * 504, sizeof(double));
   for (int32_t e = 0; e < nelem; ++e) {
-    if (lat[e].kind == ORC_QUAD) orc_quad_coef(lat[e].L, lat[e].k, qcoef + 168 * e);
-    if (lat[e].kind == ORC_MAP2) memcpy(qcoef + 168 * e, lat[e].coef, 168 * sizeof(double));
+    if (lat[e].kind == ORC_QUAD && lat[e].order == 3)
+      orc_quad3_coef(lat[e].L, lat[e].k, qcoef + 504 * e);
+    else if (lat[e].kind == ORC_QUAD)
+      orc_quad_coef(lat[e].L, lat[e].k, qcoef + 504 * e);
+    if (lat[e].kind == ORC_MAP2) memcpy(qcoef + 504 * e, lat[e].coef, 168 * sizeof(double));
+    if (lat[e].kind == ORC_MAP3) memcpy(qcoef + 504 * e, lat[e].coef, 504 * sizeof(double));
   }
   for (int32_t p = 0; p < passes; ++p) {
     int64_t gp = (int64_t)first_pass + p;
@@ -822,7 +932,13 @@ int64_t orc_track(orc_beam *b, const orc_elem *lat, int32_t nelem, int32_t passe
         switch (el->kind) {
           case ORC_EDRIFT: edrift(z, el->L); break;
           case ORC_QUAD:
-          case ORC_MAP2: map2(z, qcoef + 168 * e); break;
+            if (el->order == 3)
+              map3(z, qcoef + 504 * e);
+            else
+              map2(z, qcoef + 504 * e);
+            break;
+          case ORC_MAP2: map2(z, qcoef + 504 * e); break;
+          case ORC_MAP3: map3(z, qcoef + 504 * e); break;
           case ORC_MULT: mult(z, kn, el->order); break;
           case ORC_KQUAD: kquad(z, &kd[e]); break;
           case ORC_CSBEND: csbend(z, &kd[e]); break;

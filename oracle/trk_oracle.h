@@ -22,7 +22,7 @@ extern "C" {
 enum {
   ORC_EDRIFT = 1, ORC_QUAD = 2, ORC_MAP2 = 3, ORC_MULT = 4, ORC_KQUAD = 5,
   ORC_CSBEND = 6, ORC_RFCA = 7, ORC_WAKE = 8, ORC_RADKICK = 9, ORC_MARKER = 10,
-  ORC_TRWAKE = 11
+  ORC_TRWAKE = 11, ORC_MAP3 = 12
 };
 enum { ORC_APER_NONE = 0, ORC_APER_RECT = 1, ORC_APER_ELLIPSE = 2 };
 enum { ORC_TAG_RAD = 2 };
@@ -34,7 +34,9 @@ typedef struct orc_elem {
   double wake_A, wake_tau0, wake_omega, charge;
   double sigma;
   double ax, ay;
-  double coef[168]; /* MAP2: C[6], R[6][6], T[6][21] (pairs j<=k row-major) */
+  double coef[504]; /* MAP2: C[6], R[6][6], T[6][21] (pairs j<=k row-major);
+                       MAP3: then U[6][56] (triples j<=k<=l, lexicographic);
+                       QUAD: order 3 selects the third-order map */
 } orc_elem;
 
 typedef struct orc_beam {
@@ -57,6 +59,8 @@ double orc_gauss(uint32_t id, uint32_t step, uint32_t tag, uint64_t seed);
 
 /* second-order thick-quad map coefficients (168 doubles) */
 void orc_quad_coef(double L, double k1, double coef[168]);
+/* third-order thick-quad map coefficients (504 doubles) */
+void orc_quad3_coef(double L, double k1, double coef[504]);
 /* Yoshida-4 coefficients c[4], d[3] */
 void orc_yoshida(double c[4], double d[3]);
 

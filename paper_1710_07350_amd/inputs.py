@@ -31,7 +31,7 @@ import numpy as np
 # WAKE, TRWAKE; MAP2 is an explicit second-order transport map, RADKICK the
 # random energy kick).
 KINDS = ("EDRIFT", "QUAD", "MAP2", "MULT", "KQUAD", "CSBEND", "RFCA", "WAKE",
-         "RADKICK", "MARKER", "TRWAKE")
+         "RADKICK", "MARKER", "TRWAKE", "MAP3")
 APERTURES = ("NONE", "RECT", "ELLIPSE")
 
 C_LIGHT = 299792458.0
@@ -42,7 +42,7 @@ class Element:
     kind: str
     L: float = 0.0            # length [m]
     k: float = 0.0            # K1 [m^-2] (QUAD/KQUAD) or KnL [m^-n] (MULT)
-    order: int = 0            # MULT order n (1 quad, 2 sext, 3 oct)
+    order: int = 0            # MULT order n (1 quad, 2 sext, 3 oct); QUAD: 3 = third-order map
     nsteps: int = 1           # Yoshida-4 steps (KQUAD/CSBEND)
     angle: float = 0.0        # bend angle [rad] (CSBEND)
     volt: float = 0.0         # RF voltage [V]
@@ -54,7 +54,7 @@ class Element:
     charge: float = 0.0       # bunch charge [C]
     nbins: int = 0            # histogram bins (WAKE, TRWAKE)
     sigma: float = 0.0        # RADKICK rms energy kick
-    coef: Optional[np.ndarray] = None  # MAP2: 168 doubles C[6], R[6][6], T[6][21]
+    coef: Optional[np.ndarray] = None  # MAP2: 168 doubles C[6], R[6][6], T[6][21]; MAP3: + U[6][56]
     aperture: str = "NONE"
     ax: float = 0.0           # RECT half-width x / ELLIPSE semi-axis a [m]
     ay: float = 0.0           # RECT half-width y / ELLIPSE semi-axis b [m]
@@ -104,16 +104,18 @@ def uniform_box_beam(n: int, seed: int, half_widths: Sequence[float]) -> dict:
 # lattices
 # --------------------------------------------------------------------------
 def fodo_lattice(ncells: int = 10, k1: float = 1.2, k2l: float = 5.0,
-                 aper: float = 5e-3) -> List[Element]:
+                 aper: float = 5e-3, quad_order: int = 2) -> List[Element]:
     """10 FODO cells [D 1 m, QF 0.2 m, SF, D 1 m, QD 0.2 m, SD] with the
-    aperture |x|,|y| < 5 mm after every element (60 elements per pass)."""
+    aperture |x|,|y| < 5 mm after every element (60 elements per pass);
+    quad_order 3 tracks the quadrupoles with their third-order maps."""
     a = dict(aperture="RECT", ax=aper, ay=aper)
+    qo = 3 if quad_order == 3 else 0
     cell = [
         Element("EDRIFT", L=1.0, **a),
-        Element("QUAD", L=0.2, k=+k1, **a),
+        Element("QUAD", L=0.2, k=+k1, order=qo, **a),
         Element("MULT", k=+k2l, order=2, **a),
         Element("EDRIFT", L=1.0, **a),
-        Element("QUAD", L=0.2, k=-k1, **a),
+        Element("QUAD", L=0.2, k=-k1, order=qo, **a),
         Element("MULT", k=-k2l, order=2, **a),
     ]
     return [dataclasses.replace(e) for _ in range(ncells) for e in cell]
