@@ -39,13 +39,13 @@ WAKES = ("WAKE", "TRWAKE")
 # scaled by 2.000, WRITE_SIZE by 1.000, the factors a 1 GiB copy gives),
 # averaged over the runs of one pass (profiles/*_hbm_bytes.md); absent until
 # measured for the current kernel.
-TRAFFIC_PER_LAUNCH = {("roof", 1): 734042624}
+TRAFFIC_PER_LAUNCH = {("bc", 0): 99778975, ("roof", 1): 734042624}
 # FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
 # particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
 # run in which nobody is lost (profiles/k_run_fp64_flops.md)
 FP64_PEAK_TFLOPS = 78.6
-FP64_FLOP_PER_STEP = {"ring": 143.0, "fodo": 60.0}
+FP64_FLOP_PER_STEP = {"ring": 143.0, "fodo": 60.0, "fodo3": 72.7}
 
 
 def parse():
@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--precision", default="bf16x2", choices=["bf16", "bf16x2"])
     ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
+    ap.add_argument("--quad-order", type=int, default=2, choices=[2, 3],
+                    help="fodo/roof: track the quadrupoles with second- or third-order maps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--particles", type=float, default=None)
     ap.add_argument("--sigma-scale", type=float, default=1.0,
@@ -77,7 +79,7 @@ def run_mask_bytes(lattice, e0, e1, moments=False, next_wake=False):
         k = e.kind
         if k == "EDRIFT":
             rd |= {0, 1, 2, 3, 4}; wr |= {0, 2, 4}
-        elif k in ("QUAD", "MAP2"):
+        elif k in ("QUAD", "MAP2", "MAP3"):
             c = e.coef if e.coef is not None else None
             if k == "MAP2":
                 R = c[6:42].reshape(6, 6); T = c[42:].reshape(6, 21)
@@ -525,7 +527,7 @@ def main():
                "particles": n, "elements_per_pass": len(lat), "turns_per_step": 1}
         sample = (100_000, 40)
     else:  # fodo / roof
-        lat = inputs.fodo_lattice()
+        lat = inputs.fodo_lattice(quad_order=args.quad_order)
         n = int(args.particles or (10_000 if wl == "fodo" else 10_000_000))
         beam_kw = dict(n=n, seed=0)
         if args.sigma_scale != 1.0:
@@ -536,8 +538,10 @@ def main():
         warm = args.warmup if args.warmup is not None else 1
         fresh = True
         cfg = {"workload": f"FODO channel: {n:.0e} particles, 10 cells (60 elements) per pass, "
-                           f"{passes_per_step} passes per step",
-               "particles": n, "elements_per_pass": len(lat), "fusion_max_elements": args.fusion}
+                           f"{passes_per_step} passes per step"
+                           + (", third-order quadrupole maps" if args.quad_order == 3 else ""),
+               "particles": n, "elements_per_pass": len(lat), "fusion_max_elements": args.fusion,
+               "quad_order": args.quad_order}
         sample = (10_000, 100) if wl == "fodo" else (1_000_000, 10)
 
     L = B.Lattice(lat)
@@ -637,12 +641,15 @@ def main():
     roof = {"bound": "hbm", "kernel": "trk::k_run (fused element run)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC_PER_LAUNCH.get((wl, args.fusion)),
+            "traffic": TRAFFIC_PER_LAUNCH.get((wl, args.fusion)) if args.quad_order == 2 else None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
             "alg_bytes_per_launch": round(alg_bytes_per_launch)}
     # a launch whose FP64 work per byte exceeds the machine balance is bound by
     # the FP64 vector units: report it against their peak instead
-    fpp = FP64_FLOP_PER_STEP.get("fodo" if wl in ("fodo", "roof") else wl)
+    fkey = wl
+    if wl in ("fodo", "roof"):
+        fkey = "fodo3" if args.quad_order == 3 else "fodo"
+    fpp = FP64_FLOP_PER_STEP.get(fkey)
     if fpp is not None:
         steps_per_launch = prof_steps / max(run_launches, 1)
         flops = fpp * steps_per_launch

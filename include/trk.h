@@ -56,8 +56,12 @@ extern "C" {
 /* ------------------------------------------------------------------ elements
  * Element kinds (the beamline elements of the paper's element table, Sec. 3):
  *   TRK_EDRIFT  exact drift, length L (Sec. 2.1 listings).
- *   TRK_QUAD    thick quadrupole L, K1 as a second-order transfer matrix.
+ *   TRK_QUAD    thick quadrupole L, K1 as a second-order transfer matrix
+ *               (order 3: third order, the model's chromatic cubic terms).
  *   TRK_MAP2    explicit second-order map: coef = C[6], R[6][6], T[6][21].
+ *   TRK_MAP3    explicit third-order map (the M3 matrix tracking): coef =
+ *               C, R, T as MAP2, then U[6][56] over the monomials z_j z_k z_l,
+ *               j <= k <= l in lexicographic order.
  *   TRK_MULT    thin multipole, order n (1 quad, 2 sext, 3 oct), k = KnL.
  *   TRK_KQUAD   kick-drift quadrupole L, K1, nsteps 4th-order symplectic steps.
  *   TRK_CSBEND  canonical-kick sector bend L, angle, nsteps steps.
@@ -80,7 +84,7 @@ extern "C" {
 enum trk_kind {
   TRK_EDRIFT = 1, TRK_QUAD = 2, TRK_MAP2 = 3, TRK_MULT = 4, TRK_KQUAD = 5,
   TRK_CSBEND = 6, TRK_RFCA = 7, TRK_WAKE = 8, TRK_RADKICK = 9, TRK_MARKER = 10,
-  TRK_TRWAKE = 11
+  TRK_TRWAKE = 11, TRK_MAP3 = 12
 };
 enum trk_aperture { TRK_APER_NONE = 0, TRK_APER_RECT = 1, TRK_APER_ELLIPSE = 2 };
 enum trk_wake_mode { TRK_WAKE_FP64 = 0, TRK_WAKE_FP32_MFMA = 1 };
@@ -88,7 +92,7 @@ enum trk_wake_mode { TRK_WAKE_FP64 = 0, TRK_WAKE_FP32_MFMA = 1 };
 typedef struct trk_element {
   int32_t kind;      /* enum trk_kind */
   int32_t aperture;  /* enum trk_aperture */
-  int32_t order;     /* TRK_MULT order, 1..8 */
+  int32_t order;     /* TRK_MULT order, 1..8; TRK_QUAD 0..2 second order, 3 third */
   int32_t nsteps;    /* TRK_KQUAD/TRK_CSBEND integration steps, >= 1 */
   int32_t nbins;     /* TRK_WAKE bins, 2..TRK_MAX_BINS; TRK_TRWAKE 2..TRK_MAX_TRBINS */
   int32_t reserved;
@@ -97,7 +101,7 @@ typedef struct trk_element {
   double wake_A, wake_tau0, wake_omega, charge;
   double sigma;
   double ax, ay;
-  const double *coef; /* TRK_MAP2: 168 host doubles, copied at creation */
+  const double *coef; /* TRK_MAP2: 168, TRK_MAP3: 504 host doubles, copied at creation */
 } trk_element;
 
 #define TRK_MAX_BINS 4096

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libtrk.so")
 
 TRK_OK, TRK_EINVAL, TRK_EPTR, TRK_EHIP, TRK_ENOMEM, TRK_ERANGE = 0, -1, -2, -3, -4, -5
 KIND = {"EDRIFT": 1, "QUAD": 2, "MAP2": 3, "MULT": 4, "KQUAD": 5, "CSBEND": 6,
-        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11}
+        "RFCA": 7, "WAKE": 8, "RADKICK": 9, "MARKER": 10, "TRWAKE": 11, "MAP3": 12}
 APER = {"NONE": 0, "RECT": 1, "ELLIPSE": 2}
 WAKE_FP64, WAKE_FP32_MFMA = 0, 1
 MAX_BINS = 4096
@@ -208,6 +208,9 @@ class Lattice:
             r.sigma, r.ax, r.ay = e.sigma, e.ax, e.ay
             if e.coef is not None:
                 c = np.ascontiguousarray(e.coef, dtype=np.float64)
+                need = {"MAP2": 168, "MAP3": 504}.get(e.kind)
+                if need is not None and c.size != need:
+                    raise ValueError(f"{e.kind} needs {need} coefficients, got {c.size}")
                 keep.append(c)
                 r.coef = c.ctypes.data_as(C.POINTER(C.c_double))
         h = C.c_void_p()

@@ -201,6 +201,59 @@ void quad_coef(double L, double k1, double c[168]) {
   }
 }
 
+// index of z_j z_k z_l (j <= k <= l) among the 56 cubic monomials, lexicographic
+int triple_index(int j, int k, int l) {
+  int n = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b)
+      for (int q = b; q < 6; ++q, ++n)
+        if (a == j && b == k && q == l) return n;
+  return -1;
+}
+
+// Thick quadrupole to third order in the same paraxial model: the 168
+// coefficients above, then the chromatic cubic terms U[6][56]:
+// U_ij66 = (1/2) d^2 R_ij/d delta^2 and U_5jk6 = d T_5jk/d delta, with
+// phi = omega L, omega^2 = |k1|/(1+delta), so dphi/ddelta = -phi/2 and
+// d^2phi/ddelta^2 = 3 phi/4 at delta = 0.
+void quad3_coef(double L, double k1, double c[504]) {
+  std::memset(c, 0, 504 * sizeof(double));
+  quad_coef(L, k1, c);
+  if (k1 == 0.0) return;
+  double *U = c + 168;
+  const double w = std::sqrt(std::fabs(k1));
+  const double f = w * L, f2 = f * f;
+  const double cf = std::cos(f), sf = std::sin(f), c2 = std::cos(2.0 * f), s2 = std::sin(2.0 * f);
+  const double ch = std::cosh(f), sh = std::sinh(f), ch2 = std::cosh(2.0 * f),
+               sh2 = std::sinh(2.0 * f);
+  // per plane: U of R (11 12 21 22) and of T5 (11 12 22)
+  const double foc_U[4] = {-(f2 / 8.0) * cf - (3.0 * f / 8.0) * sf,
+                           ((f * cf - sf) - f2 * sf) / (8.0 * w),
+                           -(w / 8.0) * ((5.0 * f * cf + 3.0 * sf) - f2 * sf),
+                           -(f2 / 8.0) * cf - (3.0 * f / 8.0) * sf};
+  const double foc_S[3] = {-(w / 16.0) * ((4.0 * f - s2) - 2.0 * f * c2), (f * s2) / 4.0,
+                           -(2.0 * f * c2 - s2) / (16.0 * w)};
+  const double def_U[4] = {(f2 / 8.0) * ch + (3.0 * f / 8.0) * sh,
+                           ((f2 * sh + f * ch) - sh) / (8.0 * w),
+                           (w / 8.0) * ((5.0 * f * ch + 3.0 * sh) + f2 * sh),
+                           (f2 / 8.0) * ch + (3.0 * f / 8.0) * sh};
+  const double def_S[3] = {-(w / 16.0) * ((sh2 + 2.0 * f * ch2) - 4.0 * f), -(f * sh2) / 4.0,
+                           -(2.0 * f * ch2 - sh2) / (16.0 * w)};
+  for (int plane = 0; plane < 2; ++plane) {
+    const bool focusing = (plane == 0) == (k1 > 0.0);
+    const double *pu = focusing ? foc_U : def_U;
+    const double *ps = focusing ? foc_S : def_S;
+    const int o = 2 * plane;
+    U[(o + 0) * 56 + triple_index(o, 5, 5)] = pu[0];
+    U[(o + 0) * 56 + triple_index(o + 1, 5, 5)] = pu[1];
+    U[(o + 1) * 56 + triple_index(o, 5, 5)] = pu[2];
+    U[(o + 1) * 56 + triple_index(o + 1, 5, 5)] = pu[3];
+    U[4 * 56 + triple_index(o, o, 5)] = ps[0];
+    U[4 * 56 + triple_index(o, o + 1, 5)] = ps[1];
+    U[4 * 56 + triple_index(o + 1, o + 1, 5)] = ps[2];
+  }
+}
+
 // classification of a 168-coefficient map by its exact non-zero set
 struct Term {
   int i, j, k;  // k < 0: an R term
@@ -225,6 +278,42 @@ bool matches(const double *c, const Term *pat, int n, std::vector<double> &out) 
   }
   out.clear();
   for (int q = 0; q < n; ++q) out.push_back(c[coef_index(pat[q])]);
+  return true;
+}
+
+// third-order maps: {i, j, k, l}, k < 0 an R term, l < 0 a T term, else U
+struct Term3 {
+  int i, j, k, l;
+};
+// the third-order thick-quad pattern: P1's 24 terms, then 14 chromatic
+// cubic ones (each row's terms in evaluation order C, R, T, U)
+const Term3 kP3[38] = {
+    {0, 0, -1, -1}, {0, 1, -1, -1}, {0, 0, 5, -1}, {0, 1, 5, -1},
+    {1, 0, -1, -1}, {1, 1, -1, -1}, {1, 0, 5, -1}, {1, 1, 5, -1},
+    {2, 2, -1, -1}, {2, 3, -1, -1}, {2, 2, 5, -1}, {2, 3, 5, -1},
+    {3, 2, -1, -1}, {3, 3, -1, -1}, {3, 2, 5, -1}, {3, 3, 5, -1},
+    {4, 4, -1, -1}, {4, 0, 0, -1},  {4, 0, 1, -1}, {4, 1, 1, -1},
+    {4, 2, 2, -1},  {4, 2, 3, -1},  {4, 3, 3, -1}, {5, 5, -1, -1},
+    {0, 0, 5, 5},   {0, 1, 5, 5},   {1, 0, 5, 5},  {1, 1, 5, 5},
+    {2, 2, 5, 5},   {2, 3, 5, 5},   {3, 2, 5, 5},  {3, 3, 5, 5},
+    {4, 0, 0, 5},   {4, 0, 1, 5},   {4, 1, 1, 5},  {4, 2, 2, 5},
+    {4, 2, 3, 5},   {4, 3, 3, 5}};
+
+int coef_index3(const Term3 &t) {
+  if (t.k < 0) return 6 + 6 * t.i + t.j;
+  if (t.l < 0) return 42 + 21 * t.i + pair_index(t.j, t.k);
+  return 168 + 56 * t.i + triple_index(t.j, t.k, t.l);
+}
+
+bool matches3(const double *c, const Term3 *pat, int n, std::vector<double> &out) {
+  std::vector<char> in_pat(504, 0);
+  for (int q = 0; q < n; ++q) in_pat[coef_index3(pat[q])] = 1;
+  for (int q = 0; q < 504; ++q) {
+    const bool nz = c[q] != 0.0;
+    if (nz != static_cast<bool>(in_pat[q])) return false;
+  }
+  out.clear();
+  for (int q = 0; q < n; ++q) out.push_back(c[coef_index3(pat[q])]);
   return true;
 }
 
@@ -266,17 +355,32 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
         wr = M_X | M_Y | M_S;
         break;
       case TRK_QUAD:
-      case TRK_MAP2: {
-        double c[168];
+      case TRK_MAP2:
+      case TRK_MAP3: {
+        double c[504];
+        std::memset(c, 0, sizeof c);
+        const bool third = s.kind == TRK_MAP3 || (s.kind == TRK_QUAD && s.order == 3);
         if (s.kind == TRK_QUAD) {
           if (!(s.L > 0.0)) return bad("QUAD needs L > 0");
-          quad_coef(s.L, s.k, c);
+          if (s.order != 0 && s.order != 1 && s.order != 2 && s.order != 3)
+            return bad("QUAD order must be 0..3");
+          if (third)
+            quad3_coef(s.L, s.k, c);
+          else
+            quad_coef(s.L, s.k, c);
         } else {
-          if (s.coef == nullptr) return bad("MAP2 needs coef");
-          std::memcpy(c, s.coef, sizeof c);
+          if (s.coef == nullptr) return bad("MAP2/MAP3 needs coef");
+          std::memcpy(c, s.coef, (third ? 504 : 168) * sizeof(double));
         }
         std::vector<double> v;
-        if (matches(c, kP1, 24, v)) {
+        if (third) {
+          if (matches3(c, kP3, 38, v)) {
+            d.kind = K_MAP3_P3;
+          } else {
+            d.kind = K_MAP3_GEN;
+            v.assign(c, c + 504);
+          }
+        } else if (matches(c, kP1, 24, v)) {
           d.kind = K_MAP2_P1;
         } else if (matches(c, kP2, 8, v)) {
           d.kind = K_MAP2_P2;
@@ -292,6 +396,8 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
             if (q != i && c[6 + 6 * i + q] != 0.0) ident = false;
           for (int q = 0; q < 21 && ident; ++q)
             if (c[42 + 21 * i + q] != 0.0) ident = false;
+          for (int q = 0; q < 56 && ident; ++q)
+            if (c[168 + 56 * i + q] != 0.0) ident = false;
           if (ident) continue;
           wr |= 1u << i;
           for (int j = 0; j < 6; ++j)
@@ -300,6 +406,11 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
           for (int j = 0; j < 6; ++j)
             for (int k = j; k < 6; ++k, ++q)
               if (c[42 + 21 * i + q] != 0.0) rd |= (1u << j) | (1u << k);
+          q = 0;
+          for (int j = 0; j < 6; ++j)
+            for (int k = j; k < 6; ++k)
+              for (int l = k; l < 6; ++l, ++q)
+                if (c[168 + 56 * i + q] != 0.0) rd |= (1u << j) | (1u << k) | (1u << l);
         }
         break;
       }
@@ -694,7 +805,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         case K_WAKE:
         case K_TRWAKE: feat |= F_WAKE; break;
         case K_RADKICK: feat |= F_RNG; break;
-        case K_MAP2_GEN: feat |= F_GEN; break;
+        case K_MAP2_GEN:
+        case K_MAP3_GEN: feat |= F_GEN; break;
         default: break;
       }
       rd |= lat->rd[e];
@@ -1004,7 +1116,8 @@ extern "C" int trk_batch_create(const trk_lattice *const *lats, int32_t nvar, co
         case K_KQUAD:
         case K_CSBEND: B->feat |= F_KD; break;
         case K_RADKICK: B->feat |= F_RNG; break;
-        case K_MAP2_GEN: B->feat |= F_GEN; break;
+        case K_MAP2_GEN:
+        case K_MAP3_GEN: B->feat |= F_GEN; break;
         default: break;
       }
       B->ldmask |= L->rd[e] | L->wr[e];

@@ -6,13 +6,31 @@
 namespace trk {
 
 // Rarely executed handlers stay out of line so that their registers do not
-// count against the hot element loop.
-static __device__ __noinline__ void radkick_call(double &dp, double sigma, uint32_t pid, uint32_t gp,
-                                          uint32_t klo, uint32_t khi) {
-  dp = fma(sigma, dm::gauss(pid, gp, 2u, klo, khi), dp);
+// count against the hot element loop.  They take and return values, never
+// references: an escaping address would place the caller's coordinate array
+// in scratch memory for the whole kernel.
+struct Z6 {
+  double v[6];
+};
+static __device__ __noinline__ double radkick_call(double dp, double sigma, uint32_t pid,
+                                                  uint32_t gp, uint32_t klo, uint32_t khi) {
+  return fma(sigma, dm::gauss(pid, gp, 2u, klo, khi), dp);
 }
-static __device__ __noinline__ void map_gen_call(double (&z)[6], const double *__restrict__ c) {
-  el::map_gen(z, c);
+static __device__ __noinline__ Z6 map_gen_call(Z6 z, const double *__restrict__ c) {
+  el::map_gen(z.v, c);
+  return z;
+}
+static __device__ __noinline__ Z6 map3_gen_call(Z6 z, const double *__restrict__ c) {
+  el::map3_gen(z.v, c);
+  return z;
+}
+__device__ __forceinline__ void call_gen(double (&z)[6], const double *c, bool third) {
+  Z6 a;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a.v[k] = z[k];
+  a = third ? map3_gen_call(a, c) : map_gen_call(a, c);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) z[k] = a.v[k];
 }
 
 // Lattice records and constants are read-only and read at wave-uniform
@@ -52,7 +70,11 @@ __device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const El
     case K_MAP2_P2: el::map_p2(z, c); break;
     case K_MULT: el::mult(z, E.p0, E.ip); break;
     case K_MAP2_GEN:
-      if constexpr ((kFeat & F_GEN) != 0) map_gen_call(z, cx_pool_generic(pool, E.off));
+      if constexpr ((kFeat & F_GEN) != 0) call_gen(z, cx_pool_generic(pool, E.off), false);
+      break;
+    case K_MAP3_P3: el::map_p3(z, c); break;
+    case K_MAP3_GEN:
+      if constexpr ((kFeat & F_GEN) != 0) call_gen(z, cx_pool_generic(pool, E.off), true);
       break;
     case K_KQUAD:
       if constexpr ((kFeat & F_KD) != 0) el::kquad(z, c, E.ip);
@@ -83,7 +105,8 @@ __device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const El
       }
       break;
     case K_RADKICK:
-      if constexpr ((kFeat & F_RNG) != 0) radkick_call(z[5], E.p0, pid, gp, cx.seed_lo, cx.seed_hi);
+      if constexpr ((kFeat & F_RNG) != 0)
+        z[5] = radkick_call(z[5], E.p0, pid, gp, cx.seed_lo, cx.seed_hi);
       break;
     default: break;
   }

@@ -46,7 +46,15 @@ hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_tota
 // with integer atomics (exact, so the result is order-free).  Every block
 // reduces the (min, max) partials of the preceding kernel itself, in the same
 // order, so no extra launch is needed.
-constexpr int kHistThreads = 1024;
+#ifndef TRK_HIST_THREADS
+#define TRK_HIST_THREADS 1024
+#endif
+constexpr int kHistThreads = TRK_HIST_THREADS;
+#ifndef TRK_HIST_ITEMS
+#define TRK_HIST_ITEMS 32
+#endif
+constexpr int kHistItems = TRK_HIST_ITEMS;  // particles per thread (sets the grid)
+constexpr int kHistMaxGrid = 512;
 
 // A transverse coordinate as an integer multiple of 2^-40 m (clamped to
 // [-1, 1] m, ties to even, NaN counts 0), as a two's-complement word: sums of
@@ -156,8 +164,9 @@ hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_t
                             const double *mm_part, int mm_n, int nbins, uint32_t *counts,
                             double *range, hipStream_t st, const double *x, const double *y,
                             int64_t *dip) {
-  const int64_t want = (n_total + kHistThreads * 32 - 1) / (kHistThreads * 32);
-  const int grid = static_cast<int>(want < 1 ? 1 : (want > 256 ? 256 : want));
+  const int64_t chunk = static_cast<int64_t>(kHistThreads) * kHistItems;
+  const int64_t want = (n_total + chunk - 1) / chunk;
+  const int grid = static_cast<int>(want < 1 ? 1 : (want > kHistMaxGrid ? kHistMaxGrid : want));
   const bool d = dip != nullptr;
   // bytes of one sub-histogram; sub-histograms share at most 32 KB (48 KB
   // with the dipole words)

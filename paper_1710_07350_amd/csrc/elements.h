@@ -10,6 +10,8 @@
 //           ascending (j,k); the first term starts the sum (coefficient times
 //           coordinates), each later term is added with one fma; products
 //           z_j z_k rounded once.  A row whose only term is R_ii = 1 is exact.
+//   MAP3    MAP2, then sum_{j<=k<=l} U_ijkl z_j z_k z_l, (j,k,l) ascending,
+//           each monomial rounded as (z_j z_k) z_l (the M3 matrix tracking).
 //   MULT    thin kick Delta px - i Delta py = -(KnL/n!)(x+iy)^n on canonical
 //           px = x'(1+delta)/sqrt(1+x'^2+y'^2), back to x' = px/pz.
 //   KQUAD   4th-order symplectic kick-drift (Yoshida): kicks
@@ -73,6 +75,109 @@ __device__ __forceinline__ void map_p2(double (&z)[6], CP c) {
   a = fma(c[7], d * d, a);
   z[4] = a;
   z[5] = c[6] * d;
+}
+
+// the third-order thick-quad pattern: P1's terms, then the chromatic cubic
+// ones, each monomial rounded as (z_j z_k) z_l
+template <class CP>
+__device__ __forceinline__ void map_p3(double (&z)[6], CP c) {
+  const double x = z[0], xp = z[1], y = z[2], yp = z[3], s = z[4], d = z[5];
+  const double xd = x * d, xpd = xp * d, yd = y * d, ypd = yp * d;
+  double a;
+  a = c[0] * x; a = fma(c[1], xp, a); a = fma(c[2], xd, a); a = fma(c[3], xpd, a);
+  a = fma(c[24], xd * d, a); a = fma(c[25], xpd * d, a);
+  z[0] = a;
+  a = c[4] * x; a = fma(c[5], xp, a); a = fma(c[6], xd, a); a = fma(c[7], xpd, a);
+  a = fma(c[26], xd * d, a); a = fma(c[27], xpd * d, a);
+  z[1] = a;
+  a = c[8] * y; a = fma(c[9], yp, a); a = fma(c[10], yd, a); a = fma(c[11], ypd, a);
+  a = fma(c[28], yd * d, a); a = fma(c[29], ypd * d, a);
+  z[2] = a;
+  a = c[12] * y; a = fma(c[13], yp, a); a = fma(c[14], yd, a); a = fma(c[15], ypd, a);
+  a = fma(c[30], yd * d, a); a = fma(c[31], ypd * d, a);
+  z[3] = a;
+  const double xx = x * x, xxp = x * xp, xpxp = xp * xp;
+  const double yy = y * y, yyp = y * yp, ypyp = yp * yp;
+  a = c[16] * s;
+  a = fma(c[17], xx, a);
+  a = fma(c[18], xxp, a);
+  a = fma(c[19], xpxp, a);
+  a = fma(c[20], yy, a);
+  a = fma(c[21], yyp, a);
+  a = fma(c[22], ypyp, a);
+  a = fma(c[32], xx * d, a);
+  a = fma(c[33], xxp * d, a);
+  a = fma(c[34], xpxp * d, a);
+  a = fma(c[35], yy * d, a);
+  a = fma(c[36], yyp * d, a);
+  a = fma(c[37], ypyp * d, a);
+  z[4] = a;
+  z[5] = c[23] * d;
+}
+
+// any third-order map: as map_gen, then the cubic terms (j,k,l) ascending.
+// Loops run over monomials (rolled, with wave-uniform indices from a table)
+// with the six rows inside, so a monomial is formed once and consumed at
+// once and the evaluator keeps few registers; every row still adds its terms
+// in the order C, R, T, U, each group ascending.
+struct Triple {
+  unsigned char j, k, l;
+};
+struct TripleTable {
+  Triple t[56];
+  constexpr TripleTable() : t{} {
+    int q = 0;
+    for (int j = 0; j < 6; ++j)
+      for (int k = j; k < 6; ++k)
+        for (int l = k; l < 6; ++l, ++q)
+          t[q] = Triple{static_cast<unsigned char>(j), static_cast<unsigned char>(k),
+                        static_cast<unsigned char>(l)};
+  }
+};
+__device__ __forceinline__ double pick6(const double (&v)[6], int j) {
+  return j == 0 ? v[0] : j == 1 ? v[1] : j == 2 ? v[2] : j == 3 ? v[3] : j == 4 ? v[4] : v[5];
+}
+
+template <class CP>
+__device__ __forceinline__ void map3_gen(double (&z)[6], CP c) {
+  constexpr TripleTable kTri;
+  double in[6], a[6];
+  bool have[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    in[i] = z[i];
+    const double ci = c[i];
+    have[i] = ci != 0.0;
+    a[i] = have[i] ? ci : 0.0;
+  }
+  auto add = [&](int i, double coef, double m) {
+    if (coef != 0.0) {
+      a[i] = have[i] ? fma(coef, m, a[i]) : coef * m;
+      have[i] = true;
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) add(i, c[6 + 6 * i + j], in[j]);
+  int p = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int k = j; k < 6; ++k, ++p) {
+      const double m = in[j] * in[k];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) add(i, c[42 + 21 * i + p], m);
+    }
+#pragma unroll 1
+  for (int q = 0; q < 56; ++q) {
+    const Triple tr = kTri.t[q];
+    const double m = (pick6(in, tr.j) * pick6(in, tr.k)) * pick6(in, tr.l);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) add(i, c[168 + 56 * i + q], m);
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) z[i] = a[i];
 }
 
 // any second-order map: coefficient tests are wave-uniform branches

@@ -14,7 +14,7 @@ constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
 constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
 constexpr int kLightPPT = 2;       // particles per thread of memory-bound runs
-constexpr int kLongPPT = 2;        // ... of runs that touch only s and delta
+constexpr int kLongPPT = 4;        // ... of runs that touch only s and delta
 constexpr int kLongRunGrid = 1024; // grid-stride cap of those runs (4 blocks per CU)
 constexpr int kMaxRunGrid = 4096;  // grid-stride cap of the run kernel
 
@@ -34,6 +34,8 @@ enum DevKind : int32_t {
   K_RADKICK = 10,
   K_MARKER = 11,
   K_TRWAKE = 12,
+  K_MAP3_P3 = 13,
+  K_MAP3_GEN = 14,
 };
 
 // Element families present in a run; the run kernel is instantiated per set
@@ -56,6 +58,10 @@ static_assert(sizeof(DevElem) == 80, "DevElem layout");
 //                 s:(R55 T511 T512 T522 T533 T534 T544) delta:(R66)
 //   MAP2_P2    8: R11 R22 R33 R44 R55 R56 R66 T566
 //   MAP2_GEN 168: C[6] R[6][6] T[6][21]
+//   MAP3_P3   38: the 24 of MAP2_P1, then x:(U1166 U1266) x':(U2166 U2266)
+//                 y:(U3366 U3466) y':(U4366 U4466)
+//                 s:(U5116 U5126 U5226 U5336 U5346 U5446)
+//   MAP3_GEN 504: C[6] R[6][6] T[6][21] U[6][56]
 //   KQUAD      7: kq[4] dl[3]
 //   CSBEND    23: kA[4] kB[4] cph[3] sph[3] vers[3] rs[3] dl[3]
 // Scalars: EDRIFT p0 = L; MULT p0 = KnL/n!; RFCA p0 = k/2, p1 = sin(phase),
