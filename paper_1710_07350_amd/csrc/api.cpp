@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -334,6 +335,7 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
   if (L == nullptr) return fail(TRK_ENOMEM, "host allocation failed");
   double yc[4], yd[3];
   yoshida(yc, yd);
+  std::map<std::vector<uint64_t>, int32_t> pool_seen;
   for (int e = 0; e < n; ++e) {
     const trk_element &s = elems[e];
     DevElem d;
@@ -528,6 +530,20 @@ extern "C" int trk_lattice_create(const trk_element *elems, int32_t n, trk_latti
       rd |= M_X | M_Y;
     } else if (s.aperture != TRK_APER_NONE) {
       return bad("unknown aperture");
+    }
+    // elements with bit-identical constants share one copy in the pool: the
+    // run kernel reads them with scalar loads, and a small pool stays in
+    // the scalar cache (a ring's 80 identical bends, 2 kinds of quadrupole)
+    if (L->pool.size() > static_cast<size_t>(d.off)) {
+      std::vector<uint64_t> key(L->pool.size() - d.off);
+      std::memcpy(key.data(), L->pool.data() + d.off, key.size() * sizeof(uint64_t));
+      auto it = pool_seen.find(key);
+      if (it != pool_seen.end()) {
+        L->pool.resize(d.off);
+        d.off = it->second;
+      } else {
+        pool_seen.emplace(std::move(key), d.off);
+      }
     }
     L->rec.push_back(d);
     trk_element cp = s;
