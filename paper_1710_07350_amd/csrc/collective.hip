@@ -55,6 +55,10 @@ constexpr int kHistThreads = TRK_HIST_THREADS;
 #endif
 constexpr int kHistItems = TRK_HIST_ITEMS;  // particles per thread (sets the grid)
 constexpr int kHistMaxGrid = 512;
+#ifndef TRK_HIST_UNROLL
+#define TRK_HIST_UNROLL 8
+#endif
+constexpr int kHistUnroll = TRK_HIST_UNROLL;
 
 // A transverse coordinate as an integer multiple of 2^-40 m (clamped to
 // [-1, 1] m, ties to even, NaN counts 0), as a two's-complement word: sums of
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
   uint32_t *mine = sub + (wave % nsub) * nbins;
   unsigned long long *mined = subd + 2 * (wave % nsub) * nbins;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kHistThreads;
-  // four loads in flight per thread
-  constexpr int kU = 4;
+  // loads in flight per thread
+  constexpr int kU = kHistUnroll;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kHistThreads + threadIdx.x; i < n;
        i += kU * stride) {
     double v[kU], vx[kU], vy[kU];

@@ -204,14 +204,19 @@ int run_shape(RunArgs &a, int64_t n_total, int ppt_req, int cap_req) {
     const int64_t g = (n_total + static_cast<int64_t>(kBlock) * a.ppt - 1) / (kBlock * a.ppt);
     return static_cast<int>(g < 1 ? 1 : g);
   }
-  int ppt = ppt_req > 0 ? ppt_req : (a.longit ? kLongPPT : (light(a.feat) ? kLightPPT : 1));
+  // light runs with RF cavities or wakes on all six coordinates carry the
+  // registers of sines, square roots and divisions: one particle per thread
+  const bool rfw = !a.longit && (a.feat & (F_RF | F_WAKE)) != 0;
+  int ppt = ppt_req > 0 ? ppt_req
+                        : (a.longit ? kLongPPT : (light(a.feat) && !rfw ? kLightPPT : 1));
   if (!light(a.feat)) ppt = ppt >= 2 ? 2 : 1;
   ppt = ppt >= 8 ? 8 : (ppt >= 4 ? 4 : (ppt >= 2 ? 2 : 1));
   a.ppt = ppt;
   const int64_t want = (n_total + static_cast<int64_t>(kBlock) * ppt - 1) / (kBlock * ppt);
-  // light runs cover the array in one sweep of the grid; the others stride
-  const int64_t cap = cap_req > 0 ? cap_req
-                                  : (a.longit ? kLongRunGrid : (light(a.feat) ? want : kMaxRunGrid));
+  // streaming light runs cover the array in one sweep of the grid; the others stride
+  const int64_t cap =
+      cap_req > 0 ? cap_req
+                  : (a.longit ? kLongRunGrid : (light(a.feat) && !rfw ? want : kMaxRunGrid));
   return static_cast<int>(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
