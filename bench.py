@@ -414,6 +414,22 @@ def batch_bench(args):
            "sequential": {"value": steps / (ts / 1e3), "ms": ts},
            "batched_ms": tb, "speedup_vs_sequential": ts / tb,
            "variants_identical_to_sequential": same}
+    # the batched launch is bound by FP64 arithmetic, as the ring's run kernel
+    # (same elements): its FP64 flops per element step over the whole job
+    fl = FP64_FLOP_PER_STEP["ring"] * steps
+    ach = fl / (tb / 1e3) / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "trk::k_batch (persistent; whole batched call)",
+                       "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                       "fp64_flops_per_element_step": FP64_FLOP_PER_STEP["ring"]}
+    if not args.no_cpu_baseline:
+        # the oracle on variant 0 (its own sextupoles, beam and key), all turns
+        cv, cdt, cores = cpu_baseline(lats[0], dict(seed=1000), turns, 1e9, int(sizes[0]),
+                                      seed=int(seeds[0]))
+        out["cpu_baseline"] = {"value": cv, "unit": "particle\u00b7element steps/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"variant 0 ({int(sizes[0])} particles), {turns} turns, "
+                                         f"{cdt:.1f} s wall"}
     print(json.dumps(out))
 
 

@@ -140,8 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_cmp_count(const int64_t *__restrict_
   }
 }
 
-__device__ __forceinline__ int64_t block_scan_i64_1024(int64_t v, int64_t &total) {
-  __shared__ int64_t ws[16];
+// exclusive scan of one int64 per thread over a kScanThreads block, in
+// thread order; total receives the block sum
+constexpr int kScanThreads = 256;
+__device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t &total) {
+  __shared__ int64_t ws[kScanThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t incl = v;
 #pragma unroll
@@ -153,7 +156,8 @@ __device__ __forceinline__ int64_t block_scan_i64_1024(int64_t v, int64_t &total
   __syncthreads();
   int64_t off = 0;
   total = 0;
-  for (int w = 0; w < 16; ++w) {
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
     if (w < wave) off += ws[w];
     total += ws[w];
   }
@@ -161,10 +165,10 @@ __device__ __forceinline__ int64_t block_scan_i64_1024(int64_t v, int64_t &total
   return off + incl - v;
 }
 
-__global__ __launch_bounds__(1024) void k_cmp_scan(int64_t *__restrict__ blk, int64_t nblk,
-                                                   int64_t *__restrict__ hdr,
-                                                   int64_t *__restrict__ n_alive) {
-  const int64_t chunk = (nblk + 1023) / 1024;
+__global__ __launch_bounds__(kScanThreads) void k_cmp_scan(int64_t *__restrict__ blk, int64_t nblk,
+                                                           int64_t *__restrict__ hdr,
+                                                           int64_t *__restrict__ n_alive) {
+  const int64_t chunk = (nblk + kScanThreads - 1) / kScanThreads;
   const int64_t b0 = threadIdx.x * chunk;
   const int64_t b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
   int64_t sa = 0, sl = 0;
@@ -176,8 +180,8 @@ __global__ __launch_bounds__(1024) void k_cmp_scan(int64_t *__restrict__ blk, in
     for (int k = 0; k < 5; ++k) m[k] = r[B_LO + k] < m[k] ? r[B_LO + k] : m[k];
   }
   int64_t ta, tl;
-  int64_t oa = block_scan_i64_1024(sa, ta);
-  int64_t ol = block_scan_i64_1024(sl, tl);
+  int64_t oa = block_scan_i64(sa, ta);
+  int64_t ol = block_scan_i64(sl, tl);
   for (int64_t b = b0; b < b1; ++b) {
     int64_t *r = blk + b * kBlkStride;
     r[B_AOFF] = oa;
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_cmp_scan(int64_t *__restrict__ blk, in
     oa += r[B_ALIVE];
     ol += r[B_LOST];
   }
-  block_min_i64<5, 1024>(m);
+  block_min_i64<5, kScanThreads>(m);
   if (threadIdx.x == 0) {
     const int64_t n_old = *n_alive;
     hdr[H_NOLD] = n_old;
@@ -571,7 +575,8 @@ hipError_t launch_compact(double *const z[6], uint32_t *id, int64_t *lost_at, in
   stage.id = w.tid;
   stage.lost_at = w.tlost;
   hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, w.cmp_blk);
-  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(1024), 0, st, w.cmp_blk, nb, w.cmp_hdr, n_alive);
+  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(kScanThreads), 0, st, w.cmp_blk, nb, w.cmp_hdr,
+                     n_alive);
   hipLaunchKernelGGL(k_cmp_gather, dim3(grid), dim3(kBlock), 0, st, lost_at, w.cmp_blk, w.cmp_hdr,
                      w.key_a, w.pos_a);
   hipLaunchKernelGGL(k_cmp_sort, dim3(1), dim3(1024), 0, st, w.cmp_hdr, w.key_a, w.pos_a, w.key_b,
@@ -750,7 +755,8 @@ hipError_t launch_compact_variant(int mode, double *const z[6], uint32_t *id, in
   stage.id = w.tid;
   stage.lost_at = w.tlost;
   hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, w.cmp_blk);
-  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(1024), 0, st, w.cmp_blk, nb, w.cmp_hdr, n_alive);
+  hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(kScanThreads), 0, st, w.cmp_blk, nb, w.cmp_hdr,
+                     n_alive);
   if (mode == TRK_COMPACT_SWAP) {
     hipLaunchKernelGGL(k_swap_list, dim3(grid), dim3(kBlock), 0, st, lost_at, w.cmp_blk, w.cmp_hdr,
                        w.pos_a, w.pos_b);
