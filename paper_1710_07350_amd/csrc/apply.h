@@ -118,33 +118,63 @@ __device__ __forceinline__ void apply(const DevElem &E, ConstPool pool, const El
 
 // Runs that touch only s and delta (RF cavities, wake kicks, maps whose other
 // rows are identities, markers; no apertures): the arithmetic of apply() on
-// the two coordinates, without the registers of the other element kinds.
-template <uint32_t kFeat>
-__device__ __forceinline__ void apply_long(const DevElem &E, ConstPool pool, const ElemCtx &cx,
-                                           int p, double &s, double &d) {
+// the two coordinates, without the registers of the other element kinds,
+// applied to kP particles at once (lanes with on[q] false keep their values).
+template <uint32_t kFeat, int kP>
+__device__ __forceinline__ void apply_long_q(const DevElem &E, ConstPool pool, const ElemCtx &cx,
+                                             int p, double (&s)[kP], double (&d)[kP],
+                                             const bool (&on)[kP]) {
   switch (E.kind) {
     case K_MAP2_P2: {
       ConstPool c = pool + E.off;
-      double a = c[4] * s;
-      a = fma(c[5], d, a);
-      a = fma(c[7], d * d, a);
-      s = a;
-      d = c[6] * d;
+      const double r55 = c[4], r56 = c[5], r66 = c[6], t566 = c[7];
+#pragma unroll
+      for (int q = 0; q < kP; ++q) {
+        double a = r55 * s[q];
+        a = fma(r56, d[q], a);
+        a = fma(t566, d[q] * d[q], a);
+        if (on[q]) {
+          s[q] = a;
+          d[q] = r66 * d[q];
+        }
+      }
       break;
     }
     case K_RFCA:
       if constexpr ((kFeat & F_RF) != 0) {
         const int v = p * cx.nv + (E.vslot - cx.v0);
-        double z[6] = {0.0, 0.0, 0.0, 0.0, s, d};
-        el::rfca(z, E.p0, E.p1, E.p2, E.p3, cx.vc[v][0], cx.vc[v][1]);
-        d = z[5];
+        const double pin = cx.vc[v][0], inv_pout = cx.vc[v][1];
+#pragma unroll
+        for (int q = 0; q < kP; ++q)
+          if (on[q]) {
+            double z[6] = {0.0, 0.0, 0.0, 0.0, s[q], d[q]};
+            el::rfca(z, E.p0, E.p1, E.p2, E.p3, pin, inv_pout);
+            d[q] = z[5];
+          }
       }
       break;
     case K_WAKE:
       if constexpr ((kFeat & F_WAKE) != 0) {
         const int v = p * cx.nv + (E.vslot - cx.v0);
-        const double vs = el::wake_interp(s, cx.wake_par[0], cx.wake_par[1], cx.wake_v, E.ip);
-        d = fma(-cx.vc[v][0], vs, d);
+        const double kf = cx.vc[v][0];
+        const double smin = cx.wake_par[0], inv = cx.wake_par[1];
+        int i0[kP];
+        double w[kP], v0[kP], v1[kP];
+        // positions first, then every table read, then the kicks: the reads
+        // of all kP particles are in flight together (indices stay in
+        // [0, nbins - 2] for any s, so no lane reads out of bounds)
+#pragma unroll
+        for (int q = 0; q < kP; ++q) el::wake_pos(s[q], smin, inv, E.ip, i0[q], w[q]);
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+          v0[q] = cx.wake_v[i0[q]];
+          v1[q] = cx.wake_v[i0[q] + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+          const double vs = fma(w[q], v1[q] - v0[q], v0[q]);
+          if (on[q]) d[q] = fma(-kf, vs, d[q]);
+        }
       }
       break;
     default: break;

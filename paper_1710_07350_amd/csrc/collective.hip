@@ -74,14 +74,14 @@ __device__ __forceinline__ unsigned long long dip_quantum(double x) {
 template <bool kDip>
 __global__ __launch_bounds__(kHistThreads) void k_histogram(
     const double *__restrict__ s, const double *__restrict__ xs, const double *__restrict__ ys,
-    const int64_t *__restrict__ n_alive, const double *__restrict__ mm_part, int mm_n, int nbins,
-    int nsub, uint32_t *__restrict__ counts, unsigned long long *__restrict__ dip,
+    const int64_t *__restrict__ n_alive, int64_t n_total, const double *__restrict__ mm_part,
+    int mm_n, int nbins, int nsub, uint32_t *__restrict__ counts, unsigned long long *__restrict__ dip,
     double *__restrict__ range) {
   extern __shared__ uint32_t sub[];  // [nsub][nbins] counts; kDip: then [nsub][2][nbins] words
   __shared__ double pm[kHistThreads / 64][2];
   unsigned long long *subd =
       reinterpret_cast<unsigned long long *>(sub + ((nsub * nbins + 1) & ~1));
-  const int64_t n = *n_alive;
+  const int64_t n = min(*n_alive, n_total);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
   for (int j = threadIdx.x; j < mm_n; j += kHistThreads) {
@@ -183,10 +183,10 @@ hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_t
   auto *du = reinterpret_cast<unsigned long long *>(dip);
   if (d)
     hipLaunchKernelGGL(k_histogram<true>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
-                       n_alive, mm_part, mm_n, nbins, nsub, counts, du, range);
+                       n_alive, n_total, mm_part, mm_n, nbins, nsub, counts, du, range);
   else
     hipLaunchKernelGGL(k_histogram<false>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
-                       n_alive, mm_part, mm_n, nbins, nsub, counts, du, range);
+                       n_alive, n_total, mm_part, mm_n, nbins, nsub, counts, du, range);
   return hipGetLastError();
 }
 

@@ -329,21 +329,28 @@ __device__ __forceinline__ void rfca(double (&z)[6], double hk, double sph, doub
   z[5] = num * inv_pout;
 }
 
-// V(s): linear between bin centres, constant beyond the first and last
-__device__ __forceinline__ double wake_interp(double s, double smin, double inv,
-                                              const double *__restrict__ v, int nbins) {
+// V(s): linear between bin centres, constant beyond the first and last.
+// wake_pos gives the left bin i0 (always in [0, nbins - 2]) and the weight w.
+__device__ __forceinline__ void wake_pos(double s, double smin, double inv, int nbins, int &i0,
+                                         double &w) {
   const double f = (s - smin) * inv - 0.5;
   const double fl = floor(f);
-  int i0;
   if (!(fl >= 0.0))
     i0 = 0;
   else if (fl > static_cast<double>(nbins - 2))
     i0 = nbins - 2;
   else
     i0 = static_cast<int>(fl);
-  double w = f - static_cast<double>(i0);
+  w = f - static_cast<double>(i0);
   if (!(w >= 0.0)) w = 0.0;
   if (w > 1.0) w = 1.0;
+}
+
+__device__ __forceinline__ double wake_interp(double s, double smin, double inv,
+                                              const double *__restrict__ v, int nbins) {
+  int i0;
+  double w;
+  wake_pos(s, smin, inv, nbins, i0, w);
   const double v0 = v[i0];
   return fma(w, v[i0 + 1] - v0, v0);
 }

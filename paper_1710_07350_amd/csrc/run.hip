@@ -24,23 +24,115 @@
 
 namespace trk {
 
+// s/delta-only runs (RF cavities, wake kicks, longitudinal maps), software
+// pipelined: the (s, delta) of a thread's next kP particles are loaded before
+// the current kP go through the elements, so each wave keeps its next loads
+// in flight while it computes.  The element switch sits outside the particle
+// loop, so the wake-table reads of all kP particles are issued together.
+template <uint32_t kFeat, int kP, bool kNT>
+__device__ __forceinline__ void run_long(const RunArgs &a) {
+  const ConstElems elems = (ConstElems)a.elems;
+  const ConstPool pool = (ConstPool)a.pool;
+  const ElemCtx cx{a.vc, a.nv, a.v0, a.wake_v, a.wake_par, a.seed_lo, a.seed_hi};
+  const int64_t n = min(*a.n_alive, a.n_total);
+  if (a.zero_buf != nullptr && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < a.zero_n; i += kBlock) a.zero_buf[i] = 0u;
+
+  double smin = __builtin_huge_val(), smax = -__builtin_huge_val();
+  const int64_t nthr = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t step = nthr * kP;
+  const int64_t ntot = a.n_total;
+  double *const zs = a.z[4];
+  double *const zd = a.z[5];
+  double ns[kP], nd[kP];
+  // the first loads are bounded by the array length, so they need not wait
+  // for the device-side particle count; later ones by the count
+#pragma unroll
+  for (int q = 0; q < kP; ++q) {
+    const int64_t i = first + q * nthr;
+    const bool inb = i < ntot;
+    if constexpr (kNT) {
+      ns[q] = inb ? __builtin_nontemporal_load(zs + i) : 0.0;
+      nd[q] = inb ? __builtin_nontemporal_load(zd + i) : 0.0;
+    } else {
+      ns[q] = inb ? zs[i] : 0.0;
+      nd[q] = inb ? zd[i] : 0.0;
+    }
+  }
+  for (int64_t base = first; base < n; base += step) {
+    double sv[kP], dv[kP];
+    bool act[kP];
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+      sv[q] = ns[q];
+      dv[q] = nd[q];
+      act[q] = base + q * nthr < n;
+    }
+    const int64_t nb = base + step;
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+      const int64_t i = nb + q * nthr;
+      const bool inb = i < n;
+      if constexpr (kNT) {
+        ns[q] = inb ? __builtin_nontemporal_load(zs + i) : 0.0;
+        nd[q] = inb ? __builtin_nontemporal_load(zd + i) : 0.0;
+      } else {
+        ns[q] = inb ? zs[i] : 0.0;
+        nd[q] = inb ? zd[i] : 0.0;
+      }
+    }
+    for (int p = 0; p < a.npass; ++p)
+      for (int e = a.e0; e < a.e1; ++e) apply_long_q<kFeat, kP>(elems[e], pool, cx, p, sv, dv, act);
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+      if (!act[q]) continue;
+      const int64_t i = base + q * nthr;
+      if ((a.stmask >> 4) & 1u) {
+        if constexpr (kNT)
+          __builtin_nontemporal_store(sv[q], zs + i);
+        else
+          zs[i] = sv[q];
+      }
+      if ((a.stmask >> 5) & 1u) {
+        if constexpr (kNT)
+          __builtin_nontemporal_store(dv[q], zd + i);
+        else
+          zd[i] = dv[q];
+      }
+      smin = fmin(smin, sv[q]);
+      smax = fmax(smax, sv[q]);
+    }
+  }
+  if (a.mm_part != nullptr) {
+    block_minmax(smin, smax);
+    if (threadIdx.x == 0) {
+      a.mm_part[2 * blockIdx.x] = smin;
+      a.mm_part[2 * blockIdx.x + 1] = smax;
+    }
+  }
+}
+
 // kP particles per thread, strided by the grid size so every load and store
 // stays coalesced; the kP particles go through each element together, so an
 // element record is read once per kP particles and the loads of all kP are
 // in flight at once.  Loads are issued for indices below the array length
 // before the device-side particle count arrives (they stay in bounds), so
 // the count's latency is not paid twice.  kLong: the run reads and writes
-// only s and delta (RF cavities, wake kicks, longitudinal maps), so only
-// those two coordinates are loaded and kept in registers.  The moments
-// variant makes one pass over the grid with kP particles per thread, so
-// that every thread reaches the per-pass block reductions.  kNT: the
-// coordinates are streamed with non-temporal loads and stores.
+// only s and delta, handled by run_long.  The moments variant makes one pass
+// over the grid with kP particles per thread, so that every thread reaches
+// the per-pass block reductions.  kNT: the coordinates are streamed with
+// non-temporal loads and stores.
 template <uint32_t kFeat, bool kMom, int kP, bool kLong, bool kNT = false>
 __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
+  if constexpr (kLong) {
+    run_long<kFeat, kP, kNT>(a);
+    return;
+  }
   const ConstElems elems = (ConstElems)a.elems;
   const ConstPool pool = (ConstPool)a.pool;
   const ElemCtx cx{a.vc, a.nv, a.v0, a.wake_v, a.wake_par, a.seed_lo, a.seed_hi};
-  const int64_t n = *a.n_alive;
+  const int64_t n = min(*a.n_alive, a.n_total);
   if (a.zero_buf != nullptr && blockIdx.x == 0)
     for (int i = threadIdx.x; i < a.zero_n; i += kBlock) a.zero_buf[i] = 0u;
 
@@ -61,27 +153,25 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       const bool inb = i < ntot;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const bool want = kLong ? (k >= 4) : ((a.ldmask >> k) & 1u) != 0;
+        const bool want = ((a.ldmask >> k) & 1u) != 0;
         if constexpr (kNT)
           z[q][k] = (inb && want) ? __builtin_nontemporal_load(a.z[k] + i) : 0.0;
         else
           z[q][k] = (inb && want) ? a.z[k][i] : 0.0;
       }
-      pid[q] = (!kLong && inb && ((a.ldmask >> 6) & 1u)) ? a.id[i] : 0u;
+      pid[q] = (inb && ((a.ldmask >> 6) & 1u)) ? a.id[i] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kP; ++q) {
       act[q] = base + q * nthr < n;
-      if constexpr (!kLong) {
-        // A particle lost earlier in the same call still holds its slot.  The
-        // 64 slots of a wave share one loss flag (a wave-uniform load); only
-        // flagged groups read the loss records.
-        if (a.chk_lost) {
-          int64_t g = __builtin_amdgcn_readfirstlane(static_cast<int>((base + q * nthr) >> 6));
-          const int64_t glast = ntot > 0 ? (ntot - 1) >> 6 : 0;
-          g = g < 0 ? 0 : (g < glast ? g : glast);  // in bounds even with no lane active
-          if (act[q] && a.lost_flag[g] != 0u) act[q] = a.lost_at[base + q * nthr] < 0;
-        }
+      // A particle lost earlier in the same call still holds its slot.  The
+      // 64 slots of a wave share one loss flag (a wave-uniform load); only
+      // flagged groups read the loss records.
+      if (a.chk_lost) {
+        int64_t g = __builtin_amdgcn_readfirstlane(static_cast<int>((base + q * nthr) >> 6));
+        const int64_t glast = ntot > 0 ? (ntot - 1) >> 6 : 0;
+        g = g < 0 ? 0 : (g < glast ? g : glast);  // in bounds even with no lane active
+        if (act[q] && a.lost_flag[g] != 0u) act[q] = a.lost_at[base + q * nthr] < 0;
       }
       alive[q] = act[q];
       rec[q] = -1;
@@ -91,13 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       for (int e = a.e0; e < a.e1; ++e) {
         const DevElem E = elems[e];
 #pragma unroll
-        for (int q = 0; q < kP; ++q) {
-          if constexpr (kLong) {
-            if (alive[q]) apply_long<kFeat>(E, pool, cx, p, z[q][4], z[q][5]);
-          } else {
-            apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
-          }
-        }
+        for (int q = 0; q < kP; ++q)
+          apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
       }
       if constexpr (kMom) {
         double *row = a.mom_part + (static_cast<int64_t>(p) * gridDim.x + blockIdx.x) * 28;
@@ -121,14 +206,14 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       if (!act[q]) continue;
       const int64_t i = base + q * nthr;
 #pragma unroll
-      for (int k = kLong ? 4 : 0; k < 6; ++k)
+      for (int k = 0; k < 6; ++k)
         if ((a.stmask >> k) & 1u) {
           if constexpr (kNT)
             __builtin_nontemporal_store(z[q][k], a.z[k] + i);
           else
             a.z[k][i] = z[q][k];
         }
-      if (!kLong && rec[q] >= 0) {
+      if (rec[q] >= 0) {
         a.lost_at[i] = rec[q];
         a.lost_flag[i >> 6] = 1u;
       }
