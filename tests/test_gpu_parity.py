@@ -180,6 +180,20 @@ def test_bunch_compressor_fp32_mfma_within_bound(torch, n):
     print(f"FP32 wake: max |d delta| = {err_d:.3e} (bound {bd:.3e}), max |d s| = {err_s:.3e}")
 
 
+@pytest.mark.parametrize("ppt,blocks", [(4, 2), (8, 1), (1, 3), (2, 0)])
+@pytest.mark.parametrize("n", [1, 255, 4099, 30001])
+def test_longitudinal_runs_ragged(torch, n, ppt, blocks):
+    """The two-coordinate run path loads each thread's next particles while
+    the current ones go through the elements: grids capped at a few blocks
+    give several sweeps per thread and a ragged last sweep."""
+    lat = inputs.bc_lattice(nbins=64)
+    d = inputs.gaussian_beam(n, seed=n, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, run_ppt=ppt,
+                run_blocks=blocks)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+
+
 # ------------------------------------------------------------------ collective calls
 def test_histogram_bit_exact(torch):
     for n, nb in [(1, 8), (1000, 1024), (123457, 1024), (300000, 4096), (5000, 2)]:
