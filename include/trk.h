@@ -447,6 +447,19 @@ int trk_philox4x32_10(const uint32_t *ctr_dev, const uint32_t *key_dev, uint32_t
 int trk_gauss(const uint32_t *id_dev, uint32_t step, uint32_t tag, uint64_t seed,
               double *out_dev, int64_t n, void *stream);
 
+/* Machine ceilings on the box, for the rooflines.  trk_probe_stream: mode 0
+ * copies src to dst (dst[i] = src[i] + 1; n doubles read and n written),
+ * mode 1 only reads src (dst[b] = the sum of workgroup b's elements, so dst
+ * holds `blocks` doubles), mode 2 copies as mode 0 with non-temporal loads
+ * and stores; 256-thread workgroups, grid-stride, four loads in
+ * flight per lane.  trk_probe_fma: `blocks` x 256 lanes each run 8
+ * independent chains of `iters` binary64 fmas (2 flops each) and store one
+ * value, out_dev[blocks * 256].  Both enqueue one kernel; EINVAL for a bad
+ * mode, n < 0, iters < 0 or blocks outside 1..2^20, EPTR for host pointers. */
+int trk_probe_stream(const double *src_dev, double *dst_dev, int64_t n, int32_t mode,
+                     int32_t blocks, void *stream);
+int trk_probe_fma(double *out_dev, int32_t iters, int32_t blocks, void *stream);
+
 /* ------------------------------------------------------------------ misc */
 const char *trk_status_string(int status);
 const char *trk_last_error(void);

@@ -27,6 +27,7 @@ EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "t
            "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_dipole_histogram",
            "trk_trwake_convolve", "trk_trwake_kick", "trk_moments",
            "trk_compact_lost", "trk_compact_lost_mode", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
+           "trk_probe_stream", "trk_probe_fma",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
            "trk_batch_create", "trk_batch_destroy", "trk_batch_workspace_size",
            "trk_track_batched", "trk_mlp_create", "trk_mlp_destroy", "trk_mlp_get_params",
@@ -132,6 +133,8 @@ def lib():
         L.trk_elementary.argtypes = [i32, vp, vp, vp, i64, vp]
         L.trk_philox4x32_10.argtypes = [vp, vp, vp, i64, vp]
         L.trk_gauss.argtypes = [vp, u32, u32, u64, vp, i64, vp]
+        L.trk_probe_stream.argtypes = [vp, vp, i64, i32, i32, vp]
+        L.trk_probe_fma.argtypes = [vp, i32, i32, vp]
         L.trk_status_string.argtypes = [C.c_int]
         L.trk_status_string.restype = C.c_char_p
         L.trk_last_error.restype = C.c_char_p
@@ -421,6 +424,18 @@ def gauss(pid, step: int, tag: int, seed: int, stream=None):
     _check(lib().trk_gauss(pid.data_ptr(), step, tag, seed, out.data_ptr(), pid.shape[0],
                            _stream_handle(stream)))
     return out
+
+
+def probe_stream(src, dst, mode: int, blocks: int, stream=None) -> None:
+    """mode 0: dst = src + 1 (dst as long as src); mode 1: dst[:blocks] =
+    per-workgroup sums of src; mode 2: as 0 with non-temporal accesses."""
+    _check(lib().trk_probe_stream(src.data_ptr(), dst.data_ptr(), src.numel(), mode, blocks,
+                                  _stream_handle(stream)))
+
+
+def probe_fma(out, iters: int, blocks: int, stream=None) -> None:
+    """out[blocks * 256] doubles; 16 * iters flops per lane."""
+    _check(lib().trk_probe_fma(out.data_ptr(), iters, blocks, _stream_handle(stream)))
 
 
 def profile_enable(on, classes: int = 1) -> None:

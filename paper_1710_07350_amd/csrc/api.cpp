@@ -1336,6 +1336,28 @@ extern "C" int trk_gauss(const uint32_t *id_dev, uint32_t step, uint32_t tag, ui
   return TRK_OK;
 }
 
+extern "C" int trk_probe_stream(const double *src_dev, double *dst_dev, int64_t n, int32_t mode,
+                                int32_t blocks, void *stream) {
+  if (mode < 0 || mode > 2)
+    return fail(TRK_EINVAL, "mode must be 0 (copy), 1 (read) or 2 (non-temporal copy)");
+  if (n < 0) return fail(TRK_EINVAL, "n < 0");
+  if (blocks < 1 || blocks > (1 << 20)) return fail(TRK_EINVAL, "blocks must be 1..2^20");
+  if (n == 0) return TRK_OK;
+  if (int r = check_dev(src_dev, "src")) return r;
+  if (int r = check_dev(dst_dev, "dst")) return r;
+  HIP_TRY(launch_probe_stream(src_dev, dst_dev, n, mode, blocks, static_cast<hipStream_t>(stream)),
+          "stream probe");
+  return TRK_OK;
+}
+
+extern "C" int trk_probe_fma(double *out_dev, int32_t iters, int32_t blocks, void *stream) {
+  if (iters < 0) return fail(TRK_EINVAL, "iters < 0");
+  if (blocks < 1 || blocks > (1 << 20)) return fail(TRK_EINVAL, "blocks must be 1..2^20");
+  if (int r = check_dev(out_dev, "out")) return r;
+  HIP_TRY(launch_probe_fma(out_dev, iters, blocks, static_cast<hipStream_t>(stream)), "fma probe");
+  return TRK_OK;
+}
+
 // ------------------------------------------------------------------ misc
 extern "C" const char *trk_status_string(int status) {
   switch (status) {

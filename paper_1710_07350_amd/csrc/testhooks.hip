@@ -66,4 +66,72 @@ hipError_t launch_gauss(const uint32_t *id, uint32_t step, uint32_t tag, uint64_
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- machine probes
+// Streaming ceiling: mode 0 copies (dst = src + 1: n doubles read, n
+// written), mode 1 only reads (per-workgroup sums into dst[blockIdx.x]),
+// mode 2 copies with non-temporal loads and stores.  Four loads in flight
+// per lane, grid-stride over 8-byte elements.
+__global__ __launch_bounds__(256) void k_probe_stream(const double *__restrict__ src,
+                                                      double *__restrict__ dst, int64_t n,
+                                                      int mode) {
+  const int64_t nthr = static_cast<int64_t>(gridDim.x) * 256;
+  double acc = 0.0;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; base < n;
+       base += 4 * nthr) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + q * nthr;
+      v[q] = i < n ? (mode == 2 ? __builtin_nontemporal_load(src + i) : src[i]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + q * nthr;
+      if (mode == 0) {
+        if (i < n) dst[i] = v[q] + 1.0;
+      } else if (mode == 2) {
+        if (i < n) __builtin_nontemporal_store(v[q] + 1.0, dst + i);
+      } else {
+        acc += v[q];
+      }
+    }
+  }
+  if (mode == 1) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) dst[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+  }
+}
+
+// FP64 FMA ceiling: 8 independent chains of `iters` fmas per lane (2 flops
+// each); one result per lane is stored so nothing is dead.
+__global__ __launch_bounds__(256) void k_probe_fma(double *__restrict__ out, int iters) {
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = 1.0 + 1e-3 * (threadIdx.x + k);
+  const double b = 0.999999, c = 1e-7;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = fma(a[k], b, c);
+  }
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r += a[k];
+  out[static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x] = r;
+}
+
+hipError_t launch_probe_stream(const double *src, double *dst, int64_t n, int mode, int grid,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_probe_stream, dim3(grid), dim3(256), 0, st, src, dst, n, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_fma(double *out, int iters, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_probe_fma, dim3(grid), dim3(256), 0, st, out, iters);
+  return hipGetLastError();
+}
+
 }  // namespace trk

@@ -195,5 +195,9 @@ hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out
                          hipStream_t st);
 hipError_t launch_gauss(const uint32_t *id, uint32_t step, uint32_t tag, uint64_t seed,
                         double *out, int64_t n, hipStream_t st);
+// machine probes: streaming (mode 0 copy, 1 read-only) and FP64 FMA ceilings
+hipError_t launch_probe_stream(const double *src, double *dst, int64_t n, int mode, int grid,
+                               hipStream_t st);
+hipError_t launch_probe_fma(double *out, int iters, int grid, hipStream_t st);
 
 }  // namespace trk

@@ -62,3 +62,24 @@ def test_gauss_bit_equal(torch):
     got = B.gauss(torch.tensor(ids.view(np.int32), device="cuda"), 17, 2, seed).cpu().numpy()
     ref = np.array([oracle.gauss(int(i), 17, 2, seed) for i in ids])
     assert np.array_equal(got.view(np.int64), ref.view(np.int64))
+
+
+def test_machine_probes(torch):
+    """The ceiling probes compute what they claim (their timing is the
+    peak-probe script's business)."""
+    n = 100_003
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for mode in (0, 2):
+        dst.zero_()
+        B.probe_stream(src, dst, mode, 7)
+        assert torch.equal(dst, src + 1.0)
+    part = torch.zeros(7, dtype=torch.float64, device="cuda")
+    B.probe_stream(src, part, 1, 7)
+    assert float(part.sum()) == n * (n - 1) / 2
+    out = torch.empty(3 * 256, dtype=torch.float64, device="cuda")
+    B.probe_fma(out, 10, 3)
+    a = 1.0 + 1e-3 * np.add.outer(np.arange(256), np.arange(8))
+    for _ in range(10):
+        a = a * 0.999999 + 1e-7
+    assert np.allclose(out.cpu().numpy()[:256], a.sum(axis=1), rtol=1e-14)
