@@ -45,7 +45,7 @@ TRAFFIC_PER_LAUNCH = {("bc", 0): 99786251, ("roof", 1): 734042624}
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
 # run in which nobody is lost (profiles/k_run_fp64_flops.md)
 FP64_PEAK_TFLOPS = 78.6
-FP64_FLOP_PER_STEP = {"ring": 143.0, "fodo": 60.0, "fodo3": 72.7}
+FP64_FLOP_PER_STEP = {"ring": 135.8, "fodo": 60.0, "fodo3": 72.7}
 
 
 def parse():

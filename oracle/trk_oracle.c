@@ -469,14 +469,20 @@ static void mult(double *z, double kn, int order) {
   to_slopes(z, opd2, px, py);
 }
 
-/* canonical exact drift over dl (field-free Hamiltonian) */
+/* canonical exact drift over dl (field-free Hamiltonian): x, y advance by
+ * dl px/pz, dl py/pz; the path excess dl ((1+delta)/pz - 1) is written
+ * cancellation-free as dl q / (pz ((1+delta) + pz)), q = px^2 + py^2.  Both
+ * come from the one quotient w = dl / (pz ((1+delta) + pz)):
+ * dl/pz = ((1+delta) + pz) w and the excess is q w. */
 static void cdrift(double *z, double *px, double *py, double opd, double opd2, double dl) {
   double q = fma(*px, *px, *py * *py);
   double pz = sqrt(opd2 - q);
-  double t = dl / pz;
+  double a = opd + pz;
+  double w = dl / (pz * a);
+  double t = a * w;
   z[0] = fma(*px, t, z[0]);
   z[2] = fma(*py, t, z[2]);
-  z[4] = fma(q, t / (opd + pz), z[4]);
+  z[4] = fma(q, w, z[4]);
 }
 
 typedef struct {

@@ -266,18 +266,23 @@ __device__ __forceinline__ void trwake(double (&z)[6], double kfac, double ux, d
   slopes(z, c);
 }
 
+// x, y advance by dl px/pz, dl py/pz and s by the cancellation-free excess
+// dl q / (pz (opd + pz)): both from the one quotient w = dl / (pz (opd + pz))
 __device__ __forceinline__ void canon_drift(double (&z)[6], Canon &c, double dl) {
   const double q = fma(c.px, c.px, c.py * c.py);
   const double pz = sqrt(c.opd2 - q);
-  const double t = dl / pz;
+  const double a = c.opd + pz;
+  const double w = dl / (pz * a);
+  const double t = a * w;
   z[0] = fma(c.px, t, z[0]);
   z[2] = fma(c.py, t, z[2]);
-  z[4] = fma(q, t / (c.opd + pz), z[4]);
+  z[4] = fma(q, w, z[4]);
 }
 
 template <class CP>
 __device__ __forceinline__ void kquad(double (&z)[6], CP k, int nsteps) {
   Canon c = canonical(z);
+  const double iopd = 1.0 / c.opd;
   for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
