@@ -491,8 +491,9 @@ def compact_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this "
-              "single-GPU build (the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported; the "
+              "library tracks a beam on one device (a beam sharded by particle index over "
+              "several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "surr":
         return surrogate_bench(args)
