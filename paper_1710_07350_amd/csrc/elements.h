@@ -282,7 +282,6 @@ __device__ __forceinline__ void canon_drift(double (&z)[6], Canon &c, double dl)
 template <class CP>
 __device__ __forceinline__ void kquad(double (&z)[6], CP k, int nsteps) {
   Canon c = canonical(z);
-  const double iopd = 1.0 / c.opd;
   for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
