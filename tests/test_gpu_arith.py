@@ -31,6 +31,33 @@ def test_sqrt_and_division_correctly_rounded(torch):
     assert np.array_equal(q.view(np.int64), (x / y).view(np.int64))
 
 
+def test_sqrt_and_division_correctly_rounded_2e8(torch):
+    """2e8 operand pairs, in chunks of 1e7: random bit patterns of finite
+    binary64 values over the whole range (subnormals included), and the
+    operand ranges the element kernels divide and take roots in (pz near 1,
+    path lengths, slope squares).  Every quotient and root is compared bit
+    for bit with the CPU's IEEE operations."""
+    rng = np.random.default_rng(1)
+    m = 10_000_000
+    top = np.int64(0x7FEFFFFFFFFFFFFF)          # largest finite
+    for chunk in range(20):
+        if chunk % 2 == 0:
+            bits = rng.integers(0, top, m, dtype=np.int64, endpoint=True)
+            x = bits.view(np.float64) * rng.choice([-1.0, 1.0], m)
+            y = rng.integers(1, top, m, dtype=np.int64, endpoint=True).view(np.float64)
+            r = np.abs(x)
+        else:
+            x = rng.uniform(-2.0, 2.0, m)
+            y = 1.0 + rng.uniform(-0.1, 0.1, m)
+            r = 1.0 - rng.uniform(0.0, 1e-4, m)
+        q = B.elementary(5, torch.tensor(x, device="cuda"), torch.tensor(y, device="cuda"))
+        sq = B.elementary(4, torch.tensor(r, device="cuda"))
+        with np.errstate(over="ignore", under="ignore"):
+            ref_q = x / y
+        assert np.array_equal(q.cpu().numpy().view(np.int64), ref_q.view(np.int64)), chunk
+        assert np.array_equal(sq.cpu().numpy().view(np.int64), np.sqrt(r).view(np.int64)), chunk
+
+
 @pytest.mark.parametrize("fn,dom", [(0, (-9.0, 9.0)), (1, (-9.0, 9.0)), (2, (1e-300, 1.0)),
                                     (3, (-720.0, 5.0))])
 def test_own_functions_bit_equal_to_oracle(torch, fn, dom):
