@@ -111,6 +111,16 @@ def test_rfcw_lattice_fp64_bit_exact(torch, kw):
     assert np.abs(r["z"][1] - d["z"][1]).max() > 1e-9       # the transverse wake acts
 
 
+def test_rfcw_full_size_fp64_bit_exact(torch):
+    """The benchmarked transverse-wake lattice at its full size (4e6
+    particles, 1024 bins), binary64 wakes: bit-exact with the oracle."""
+    lat = inputs.rfcw_lattice()
+    d = inputs.gaussian_beam(4_000_000, seed=0, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+
+
 def test_trwake_after_losses(torch):
     """Apertures lose particles before a transverse wake within one call:
     the lazily compacted beam is packed before the dipole histogram."""
@@ -127,14 +137,14 @@ def test_trwake_after_losses(torch):
         assert_bit_exact(g, r)
 
 
-def test_rfcw_fp32_mfma_within_bound(torch):
+@pytest.mark.parametrize("n", [400_000, 4_000_000])
+def test_rfcw_fp32_mfma_within_bound(torch, n):
     """FP32 matrix-core wakes: losses, ids and x, y are identical; the slopes
     stay within the bound of the FP32 convolutions.  x, y and s do not move
     before the chicane, so every transverse wake sees the dipole sums of the
     initial beam; each V errs by at most (nbins + 3) 2^-24 sum_j |D_j W[i-j]|
     and the kick passes that on scaled by kfac / pz."""
     lat = inputs.rfcw_lattice()
-    n = 400_000
     d = inputs.gaussian_beam(n, seed=6, chirp=inputs.BC_CHIRP)
     d["z"][0] += 1e-4
     g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA)
