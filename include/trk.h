@@ -143,6 +143,11 @@ typedef struct trk_opts {
                                    loads and stores, -1 cached, 0 automatic
                                    (non-temporal when the coordinates the run
                                    touches exceed 256 MB) */
+  int32_t run_hist;             /* 0 automatic: a run that changes neither s nor
+                                   the alive set (RF and wake kicks, markers, no
+                                   apertures) bins the histogram of a following
+                                   TRK_WAKE itself; -1 never; the results are
+                                   the same */
   double p_ref_eV;              /* reference momentum at the entry of the first
                                    pass [eV/c]; raised by V cos(phase) per RFCA */
   double *moments;              /* NULL or device [passes][28]: per pass, after its

@@ -66,7 +66,7 @@ class Opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first_pass", C.c_int32),
                 ("passes_per_launch", C.c_int32), ("max_elems_per_launch", C.c_int32),
                 ("wake_mode", C.c_int32), ("run_ppt", C.c_int32), ("run_blocks", C.c_int32),
-                ("run_longit", C.c_int32), ("run_nt", C.c_int32),
+                ("run_longit", C.c_int32), ("run_nt", C.c_int32), ("run_hist", C.c_int32),
                 ("p_ref_eV", C.c_double), ("moments", C.c_void_p)]
 
 
@@ -311,12 +311,14 @@ class Workspace:
 def track(beam: Beam, lattice: Lattice, passes: int, ws: Workspace, seed: int = 0,
           first_pass: int = 0, p_ref: float = 1e9, moments=None, wake_mode: int = WAKE_FP64,
           passes_per_launch: int = 0, max_elems_per_launch: int = 0, run_ppt: int = 0,
-          run_blocks: int = 0, run_longit: int = 0, run_nt: int = 0, stream=None) -> None:
+          run_blocks: int = 0, run_longit: int = 0, run_nt: int = 0, run_hist: int = 0,
+          stream=None) -> None:
     o = Opts()
     o.run_ppt = run_ppt
     o.run_blocks = run_blocks
     o.run_longit = run_longit
     o.run_nt = run_nt
+    o.run_hist = run_hist
     o.seed = seed
     o.first_pass = first_pass
     o.passes_per_launch = passes_per_launch

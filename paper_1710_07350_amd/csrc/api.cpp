@@ -608,6 +608,7 @@ Workspace carve(void *base, int64_t n_total, size_t *bytes) {
   w.dip = base ? reinterpret_cast<int64_t *>(w.counts + TRK_MAX_BINS + 64) : nullptr;
   w.lost_flag = c.take<uint32_t>((n + 63) / 64);
   w.range = c.take<double>(2);
+  for (int k = 0; k < 2; ++k) w.hcounts[k] = c.take<uint32_t>(kHistCopies * TRK_MAX_BINS);
   w.wake_par = c.take<double>(2);
   w.wake_v = c.take<double>(2 * TRK_MAX_BINS);
   w.mom_shift = c.take<double>(6);
@@ -751,9 +752,35 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   // alive set packed, or the call ends.  The final layout does not depend on
   // when compaction runs.
   bool dirty = false;
+  // A run that changes neither s nor the alive set (RF kicks, wake kicks and
+  // markers, no apertures) bins the histogram of a longitudinal wake that
+  // follows it, over the range of the last histogram: nothing since has
+  // moved s or lost a particle, so that range is the beam's (exactly).
+  // range_ok: w.range describes the current beam; fused_buf: the buffer the
+  // previous run binned the coming wake's histogram into (-1: none); hnext:
+  // the buffer the next such run bins into (the two alternate, so a
+  // convolution can read one while clearing the other).
+  bool range_ok = false;
+  int fused_buf = -1, hnext = 0;
   for (size_t li = 0; li < plan.size(); ++li) {
     const Launch &L = plan[li];
     const bool starts_wake = is_wake(lat->src[L.e0].kind);
+    // does the next launch start with a wake?
+    bool next_wake = false, next_tr = false;
+    int next_nb = 0;
+    if (li + 1 < plan.size()) {
+      next_wake = is_wake(lat->src[plan[li + 1].e0].kind);
+      next_tr = lat->src[plan[li + 1].e0].kind == TRK_TRWAKE;
+      next_nb = lat->src[plan[li + 1].e0].nbins;
+    }
+    const bool lmom = mom && L.e1 == nelem;
+    bool s_fixed = true;  // no element of the run moves s or loses particles
+    for (int e = L.e0; e < L.e1; ++e) {
+      const int k = lat->rec[e].kind;
+      if ((k != K_RFCA && k != K_WAKE && k != K_MARKER) || lat->aper[e]) s_fixed = false;
+    }
+    const bool fuse_hist = opts->run_hist >= 0 && opts->run_longit >= 0 && next_wake &&
+                           !next_tr && s_fixed && !lmom && (starts_wake || (range_ok && !dirty));
     if (starts_wake) {
       const bool tr = lat->src[L.e0].kind == TRK_TRWAKE;
       if (dirty) {
@@ -762,39 +789,47 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         dirty = false;
       }
       const int nb = lat->src[L.e0].nbins;
-      if (prev_mm_n == 0) {
+      const bool have_hist = !tr && fused_buf >= 0;
+      if (!have_hist && prev_mm_n == 0) {
         prev_mm_n = grid_stride_blocks(beam->n_total);
         HIP_TRY(launch_minmax(beam->s, beam->n_alive, beam->n_total, w.mm_part, prev_mm_n, w.counts,
                               zero_words(tr), st),
                 "minmax");
       }
-      HIP_TRY(profiled(2, st,
-                       [&] {
-                         return launch_histogram(beam->s, beam->n_alive, beam->n_total, w.mm_part,
-                                                 prev_mm_n, nb, w.counts, w.range, st,
-                                                 tr ? beam->x : nullptr, tr ? beam->y : nullptr,
-                                                 tr ? w.dip : nullptr);
-                       }),
-              "histogram");
+      if (!have_hist) {
+        HIP_TRY(profiled(2, st,
+                         [&] {
+                           return launch_histogram(beam->s, beam->n_alive, beam->n_total,
+                                                   w.mm_part, prev_mm_n, nb, w.counts, w.range, st,
+                                                   tr ? beam->x : nullptr, tr ? beam->y : nullptr,
+                                                   tr ? w.dip : nullptr);
+                         }),
+                "histogram");
+        range_ok = true;
+      }
+      // the run after this convolution bins the next histogram into
+      // w.hcounts[hnext]: the convolution clears it
+      uint32_t *clear = fuse_hist ? w.hcounts[hnext] : nullptr;
+      const int nclear = fuse_hist ? kHistCopies * next_nb : 0;
       HIP_TRY(profiled(3, st,
                        [&] {
                          const trk_element &s = lat->src[L.e0];
                          if (tr)
                            return launch_convolve_tr(w.dip, nb, w.range, s.wake_tau0, s.wake_omega,
                                                      opts->wake_mode, w.wake_v, w.wake_par, st);
+                         if (have_hist)
+                           return launch_convolve(w.hcounts[fused_buf], nb, w.range, s.wake_tau0,
+                                                  s.wake_omega, opts->wake_mode, w.wake_v,
+                                                  w.wake_par, st, kHistCopies, clear, nclear);
                          return launch_convolve(w.counts, nb, w.range, s.wake_tau0, s.wake_omega,
-                                                opts->wake_mode, w.wake_v, w.wake_par, st);
+                                                opts->wake_mode, w.wake_v, w.wake_par, st, 1,
+                                                clear, nclear);
                        }),
               "convolve");
+      fused_buf = -1;
+    } else if (fuse_hist) {
+      HIP_TRY(launch_zero_u32(w.hcounts[hnext], kHistCopies * next_nb, st), "histogram buffer");
     }
-    // does the next launch start with a wake?
-    bool next_wake = false, next_tr = false;
-    if (li + 1 < plan.size()) {
-      next_wake = is_wake(lat->src[plan[li + 1].e0].kind);
-      next_tr = lat->src[plan[li + 1].e0].kind == TRK_TRWAKE;
-    }
-    const bool lmom = mom && L.e1 == nelem;
-
     RunArgs a;
     std::memset(&a, 0, sizeof a);
     for (int k = 0; k < 6; ++k) a.z[k] = z[k];
@@ -869,13 +904,23 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         8.0 * __builtin_popcount((a.ldmask | a.stmask) & M_ALL) * static_cast<double>(beam->n_total);
     a.nt = opts->run_nt > 0 ? 1 : (opts->run_nt < 0 ? 0 : (touched > kStreamBytes ? 1 : 0));
     const int grid = run_shape(a, beam->n_total, opts->run_ppt, opts->run_blocks);
-    if (next_wake) {
+    const bool binned = fuse_hist && a.longit;
+    if (binned) {
+      a.hist_out = w.hcounts[hnext];
+      a.hist_range = w.range;
+      a.hist_nbins = next_nb;
+    } else if (next_wake) {
       a.mm_part = w.mm_part;
       a.zero_buf = w.counts;
       a.zero_n = zero_words(next_tr);
     }
     HIP_TRY(profiled(0, st, [&] { return launch_run(a, grid, st); }), "run kernel");
-    prev_mm_n = next_wake ? grid : 0;
+    prev_mm_n = next_wake && !binned ? grid : 0;
+    if (binned) {
+      fused_buf = hnext;
+      hnext ^= 1;
+    }
+    if (!s_fixed) range_ok = false;
     if (lmom) {
       double *out = opts->moments + static_cast<size_t>(L.pass0) * 28;
       HIP_TRY(launch_mom_finalize(w.mom_part, grid, L.npass, w.mom_shift, out, 28, nullptr, st),

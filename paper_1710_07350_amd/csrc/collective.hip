@@ -204,12 +204,28 @@ __device__ __forceinline__ double wake_table_entry(int m, double dt, double tau0
 
 // Convolution weights: the counts, or (transverse, plane blockIdx.y) the
 // dipole sums in metres, 2^-40 times the integer (one rounding).
+// counts of bin m summed over the ncopy (<= kHistCopies) copies [ncopy][nbins]
+// (an exact integer sum; the loads are unrolled so they go out together)
+__device__ __forceinline__ uint32_t bin_count(const uint32_t *counts, int nbins, int ncopy, int m) {
+  uint32_t c = counts[m];
+#pragma unroll
+  for (int k = 1; k < kHistCopies; ++k)
+    if (k < ncopy) c += counts[k * nbins + m];
+  return c;
+}
+
 template <bool kTr>
-__device__ __forceinline__ double conv_weight(const void *src, int nbins, int m) {
+__device__ __forceinline__ double conv_weight(const void *src, int nbins, int ncopy, int m) {
   if constexpr (kTr)
     return static_cast<double>(static_cast<const long long *>(src)[blockIdx.y * nbins + m]) * 0x1p-40;
   else
-    return static_cast<double>(static_cast<const uint32_t *>(src)[m]);
+    return static_cast<double>(bin_count(static_cast<const uint32_t *>(src), nbins, ncopy, m));
+}
+
+// the first workgroup clears the buffer the following run bins into
+__device__ __forceinline__ void clear_next(uint32_t *zbuf, int zn) {
+  if (zbuf != nullptr && blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = threadIdx.x; i < zn; i += blockDim.x) zbuf[i] = 0u;
 }
 
 constexpr int kTile = 256;  // outputs per convolution workgroup
@@ -227,9 +243,11 @@ __device__ __forceinline__ void write_wake_par(double smin, double width, int nb
 // loop.  Workgroup g owns outputs [256 g, 256 g + 256) (of plane blockIdx.y).
 template <bool kTr>
 __global__ __launch_bounds__(kTile) void k_conv_fp64(const void *__restrict__ src, int nbins,
-                                                     const double *__restrict__ range, double tau0,
-                                                     double omega, double *__restrict__ v,
-                                                     double *__restrict__ wake_par) {
+                                                     int ncopy, const double *__restrict__ range,
+                                                     double tau0, double omega,
+                                                     double *__restrict__ v,
+                                                     double *__restrict__ wake_par, uint32_t *zbuf,
+                                                     int zn) {
   constexpr int kN = kTr ? TRK_MAX_TRBINS : TRK_MAX_BINS;
   __shared__ double W[kN];
   __shared__ std::conditional_t<kTr, double, uint32_t> C[kN];
@@ -241,10 +259,11 @@ __global__ __launch_bounds__(kTile) void k_conv_fp64(const void *__restrict__ sr
   for (int m = threadIdx.x; m < hi; m += kTile) {
     W[m] = wake_table_entry<kTr>(m, dt, tau0, omega);
     if constexpr (kTr)
-      C[m] = conv_weight<kTr>(src, nbins, m);
+      C[m] = conv_weight<kTr>(src, nbins, 1, m);
     else
-      C[m] = static_cast<const uint32_t *>(src)[m];
+      C[m] = bin_count(static_cast<const uint32_t *>(src), nbins, ncopy, m);
   }
+  clear_next(zbuf, zn);
   __syncthreads();
   const int i = kTile * blockIdx.x + threadIdx.x;
   if (i < nbins) {
@@ -268,8 +287,9 @@ constexpr int kConvWaves = 16;
 
 template <bool kTr>
 __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
-    const void *__restrict__ src, int nbins, const double *__restrict__ range, double tau0,
-    double omega, double *__restrict__ v, double *__restrict__ wake_par) {
+    const void *__restrict__ src, int nbins, int ncopy, const double *__restrict__ range,
+    double tau0, double omega, double *__restrict__ v, double *__restrict__ wake_par,
+    uint32_t *zbuf, int zn) {
   __shared__ float Wf[TRK_MAX_BINS];
   __shared__ float Cf[TRK_MAX_BINS];
   __shared__ float part[kConvWaves][kTile];
@@ -281,8 +301,9 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
   const int hi = kTile * (g + 1);  // entries this tile can touch
   for (int m = threadIdx.x; m < hi; m += blockDim.x) {
     Wf[m] = m < nbins ? static_cast<float>(wake_table_entry<kTr>(m, dt, tau0, omega)) : 0.0f;
-    Cf[m] = m < nbins ? static_cast<float>(conv_weight<kTr>(src, nbins, m)) : 0.0f;
+    Cf[m] = m < nbins ? static_cast<float>(conv_weight<kTr>(src, nbins, ncopy, m)) : 0.0f;
   }
+  clear_next(zbuf, zn);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, kq = lane >> 4;
@@ -313,27 +334,31 @@ __global__ __launch_bounds__(64 * kConvWaves) void k_conv_mfma(
 }
 
 template <bool kTr>
-hipError_t launch_conv(const void *src, int nbins, const double *range, double tau0, double omega,
-                       int mode, double *v, double *wake_par, hipStream_t st) {
+hipError_t launch_conv(const void *src, int nbins, int ncopy, const double *range, double tau0,
+                       double omega, int mode, double *v, double *wake_par, uint32_t *zbuf, int zn,
+                       hipStream_t st) {
   const dim3 grid((nbins + kTile - 1) / kTile, kTr ? 2 : 1);
   if (mode == TRK_WAKE_FP32_MFMA)
-    hipLaunchKernelGGL(k_conv_mfma<kTr>, grid, dim3(64 * kConvWaves), 0, st, src, nbins, range,
-                       tau0, omega, v, wake_par);
+    hipLaunchKernelGGL(k_conv_mfma<kTr>, grid, dim3(64 * kConvWaves), 0, st, src, nbins, ncopy,
+                       range, tau0, omega, v, wake_par, zbuf, zn);
   else
-    hipLaunchKernelGGL(k_conv_fp64<kTr>, grid, dim3(kTile), 0, st, src, nbins, range, tau0, omega,
-                       v, wake_par);
+    hipLaunchKernelGGL(k_conv_fp64<kTr>, grid, dim3(kTile), 0, st, src, nbins, ncopy, range, tau0,
+                       omega, v, wake_par, zbuf, zn);
   return hipGetLastError();
 }
 
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
-                           double omega, int mode, double *v, double *wake_par, hipStream_t st) {
-  return launch_conv<false>(counts, nbins, range, tau0, omega, mode, v, wake_par, st);
+                           double omega, int mode, double *v, double *wake_par, hipStream_t st,
+                           int ncopy, uint32_t *zbuf, int zn) {
+  if (ncopy < 1 || ncopy > kHistCopies) return hipErrorInvalidValue;
+  return launch_conv<false>(counts, nbins, ncopy, range, tau0, omega, mode, v, wake_par, zbuf, zn,
+                            st);
 }
 
 hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range, double tau0,
                               double omega, int mode, double *v, double *wake_par,
                               hipStream_t st) {
-  return launch_conv<true>(dip, nbins, range, tau0, omega, mode, v, wake_par, st);
+  return launch_conv<true>(dip, nbins, 1, range, tau0, omega, mode, v, wake_par, nullptr, 0, st);
 }
 
 // ------------------------------------------------------------------ wake kick

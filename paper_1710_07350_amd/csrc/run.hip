@@ -45,6 +45,18 @@ __device__ __forceinline__ void run_long(const RunArgs &a) {
   const int64_t ntot = a.n_total;
   double *const zs = a.z[4];
   double *const zd = a.z[5];
+  // the next wake's histogram, binned here when the run changes neither s
+  // nor the alive set (its range is the last histogram's, exact)
+  extern __shared__ uint32_t hsub[];
+  const bool hist = a.hist_out != nullptr;
+  double hmn = 0.0, hinv = 0.0;
+  if (hist) {
+    for (int j = threadIdx.x; j < a.hist_nbins; j += kBlock) hsub[j] = 0u;
+    hmn = a.hist_range[0];
+    const double width = a.hist_range[1] - hmn;
+    hinv = width > 0.0 ? static_cast<double>(a.hist_nbins) / width : 0.0;
+    __syncthreads();
+  }
   double ns[kP], nd[kP];
   // the first loads are bounded by the array length, so they need not wait
   // for the device-side particle count; later ones by the count
@@ -102,6 +114,18 @@ __device__ __forceinline__ void run_long(const RunArgs &a) {
       }
       smin = fmin(smin, sv[q]);
       smax = fmax(smax, sv[q]);
+      if (hist) {
+        const double f = (sv[q] - hmn) * hinv;
+        if (f >= 0.0) atomicAdd(hsub + min(static_cast<int>(f), a.hist_nbins - 1), 1u);
+      }
+    }
+  }
+  if (hist) {
+    __syncthreads();
+    uint32_t *out = a.hist_out + (blockIdx.x % kHistCopies) * a.hist_nbins;
+    for (int j = threadIdx.x; j < a.hist_nbins; j += kBlock) {
+      const uint32_t c = hsub[j];
+      if (c != 0u) atomicAdd(out + j, c);
     }
   }
   if (a.mm_part != nullptr) {
@@ -242,11 +266,13 @@ constexpr bool longit_ok(uint32_t f) { return (f & ~(F_RF | F_WAKE)) == 0; }
 
 template <uint32_t kFeat, bool kLong, bool kNT>
 void launch_ppt_nt(const RunArgs &a, int grid, hipStream_t st) {
+  // a run-binned histogram keeps its counts in LDS (two-coordinate runs only)
+  const size_t lds = kLong && a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
   switch (a.ppt) {
-    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong, kNT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
   }
 }
 

@@ -9,7 +9,10 @@
 
 namespace trk {
 
-constexpr int kBlock = 256;        // threads per block of the particle kernels
+constexpr int kBlock = 256;
+// copies of the counts a run-binned histogram merges into (spreads the
+// same-address contention of up to kMaxRunGrid workgroups)
+constexpr int kHistCopies = 8;        // threads per block of the particle kernels
 constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
 constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
@@ -93,6 +96,13 @@ struct RunArgs {
   const double *wake_v;     // V[nbins] when elements[e0] is a WAKE; Vx, Vy for a TRWAKE
   const double *wake_par;   // (smin, 1/delta)
   double *mm_part;          // [gridDim.x][2] (min s, max s) of survivors, or null
+  // Histogram of the next wake binned in this run (two-coordinate runs that
+  // change neither s nor the alive set): hist_out[kHistCopies][hist_nbins]
+  // (zeroed beforehand) receives the counts of the final s over
+  // [hist_range[0], hist_range[1]], workgroup b adding to copy b % kHistCopies.
+  uint32_t *hist_out;
+  const double *hist_range;
+  int32_t hist_nbins;
   uint32_t *zero_buf;       // zeroed by block 0 when non-null
   int32_t zero_n;
   int32_t mom;              // per-pass moment partials
@@ -129,6 +139,7 @@ struct Workspace {
   int64_t *dip;        // [2][TRK_MAX_TRBINS] (same allocation, zeroed with the counts)
   uint32_t *lost_flag; // [ceil(n/64)] loss flags of 64-slot groups
   double *range;       // [2]
+  uint32_t *hcounts[2];  // [kHistCopies][TRK_MAX_BINS] each: run-binned histograms, alternating
   double *wake_par;    // [2]
   double *wake_v;      // [2 * TRK_MAX_BINS]
   double *mom_shift;   // [6]
@@ -167,9 +178,12 @@ hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range
 hipError_t launch_trwake_kick(double *const z[6], const int64_t *n_alive, int64_t n_total,
                               const double *v, const double *wake_par, int nbins, double kfac,
                               hipStream_t st);
-// v: the convolution; wake_par: (smin, nbins/width) or null
+// v: the convolution; wake_par: (smin, nbins/width) or null.  counts holds
+// ncopy copies [ncopy][nbins] whose sum is the histogram; zbuf (or null):
+// zn words zeroed by the first workgroup (a buffer the next run bins into)
 hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *range, double tau0,
-                           double omega, int mode, double *v, double *wake_par, hipStream_t st);
+                           double omega, int mode, double *v, double *wake_par, hipStream_t st,
+                           int ncopy = 1, uint32_t *zbuf = nullptr, int zn = 0);
 hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64_t n_total,
                             const double *v, const double *wake_par, int nbins, double kfac,
                             hipStream_t st);

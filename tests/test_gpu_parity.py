@@ -161,6 +161,38 @@ def test_bunch_compressor_fp64_bit_exact(torch, n):
     assert_bit_exact(g, r)
 
 
+@pytest.mark.parametrize("kw", [dict(run_hist=-1), dict(max_elems_per_launch=1),
+                                dict(run_ppt=2, run_blocks=3)])
+def test_bunch_compressor_run_binned_histograms(torch, kw):
+    """Runs of RF and wake kicks (s and the alive set unchanged) bin the next
+    wake's histogram themselves over the last histogram's range; with that
+    off, one element per launch (the buffer cleared by its own launch
+    instead of the convolution), or a few workgroups, two passes stay
+    bit-exact with the oracle."""
+    lat = inputs.bc_lattice()
+    d = inputs.gaussian_beam(100_000, seed=2, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, **kw)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+
+
+def test_run_binned_histograms_mixed_bins(torch):
+    """Consecutive wakes with different bin counts (the range carries over,
+    the binning does not) and a marker inside the binning run."""
+    wk = dict(wake_A=1e14, wake_tau0=10e-12, wake_omega=2 * math.pi * 50e9, charge=1e-9)
+    rf = dict(volt=20e6, phase=math.radians(-20), freq=1.3e9)
+    lat = [Element("RFCA", **rf), Element("WAKE", nbins=256, **wk), Element("RFCA", **rf),
+           Element("MARKER"), Element("WAKE", nbins=1024, **wk), Element("RFCA", **rf),
+           Element("WAKE", nbins=17, **wk), Element("MAP2", coef=inputs.chicane_coef())]
+    d = inputs.gaussian_beam(50_000, seed=3, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+    f32 = [run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA, run_hist=h)
+           for h in (0, -1)]
+    assert np.array_equal(f32[0]["z"], f32[1]["z"]) and np.array_equal(f32[0]["id"], f32[1]["id"])
+
+
 @pytest.mark.parametrize("n", [100_000, 4_000_000])
 def test_bunch_compressor_fp32_mfma_within_bound(torch, n):
     lat = inputs.bc_lattice()
