@@ -205,12 +205,17 @@ __device__ __forceinline__ double wake_table_entry(int m, double dt, double tau0
 // Convolution weights: the counts, or (transverse, plane blockIdx.y) the
 // dipole sums in metres, 2^-40 times the integer (one rounding).
 // counts of bin m summed over the ncopy (<= kHistCopies) copies [ncopy][nbins]
-// (an exact integer sum; the loads are unrolled so they go out together)
+// (an exact integer sum).  Every load is unconditional, from copy k or, past
+// ncopy, from copy 0 again (always in bounds) with the value dropped, so
+// all of them are in flight together.
 __device__ __forceinline__ uint32_t bin_count(const uint32_t *counts, int nbins, int ncopy, int m) {
   uint32_t c = counts[m];
 #pragma unroll
-  for (int k = 1; k < kHistCopies; ++k)
-    if (k < ncopy) c += counts[k * nbins + m];
+  for (int k = 1; k < kHistCopies; ++k) {
+    const bool use = k < ncopy;
+    const uint32_t x = counts[(use ? k : 0) * nbins + m];
+    c += use ? x : 0u;
+  }
   return c;
 }
 
