@@ -774,13 +774,17 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
       next_nb = lat->src[plan[li + 1].e0].nbins;
     }
     const bool lmom = mom && L.e1 == nelem;
-    bool s_fixed = true;  // no element of the run moves s or loses particles
+    // no element of the run moves s or loses particles (energy kicks,
+    // transverse wake kicks, random energy kicks, markers; no apertures)
+    bool s_fixed = true;
     for (int e = L.e0; e < L.e1; ++e) {
       const int k = lat->rec[e].kind;
-      if ((k != K_RFCA && k != K_WAKE && k != K_MARKER) || lat->aper[e]) s_fixed = false;
+      const bool keeps_s = k == K_RFCA || k == K_WAKE || k == K_TRWAKE || k == K_RADKICK ||
+                           k == K_MARKER;
+      if (!keeps_s || lat->aper[e]) s_fixed = false;
     }
-    const bool fuse_hist = opts->run_hist >= 0 && opts->run_longit >= 0 && next_wake &&
-                           !next_tr && s_fixed && !lmom && (starts_wake || (range_ok && !dirty));
+    const bool fuse_hist = opts->run_hist >= 0 && next_wake && !next_tr && s_fixed && !lmom &&
+                           (starts_wake || (range_ok && !dirty));
     if (starts_wake) {
       const bool tr = lat->src[L.e0].kind == TRK_TRWAKE;
       if (dirty) {
@@ -816,7 +820,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
                          const trk_element &s = lat->src[L.e0];
                          if (tr)
                            return launch_convolve_tr(w.dip, nb, w.range, s.wake_tau0, s.wake_omega,
-                                                     opts->wake_mode, w.wake_v, w.wake_par, st);
+                                                     opts->wake_mode, w.wake_v, w.wake_par, st,
+                                                     clear, nclear);
                          if (have_hist)
                            return launch_convolve(w.hcounts[fused_buf], nb, w.range, s.wake_tau0,
                                                   s.wake_omega, opts->wake_mode, w.wake_v,
@@ -904,7 +909,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
         8.0 * __builtin_popcount((a.ldmask | a.stmask) & M_ALL) * static_cast<double>(beam->n_total);
     a.nt = opts->run_nt > 0 ? 1 : (opts->run_nt < 0 ? 0 : (touched > kStreamBytes ? 1 : 0));
     const int grid = run_shape(a, beam->n_total, opts->run_ppt, opts->run_blocks);
-    const bool binned = fuse_hist && a.longit;
+    const bool binned = fuse_hist;
     if (binned) {
       a.hist_out = w.hcounts[hnext];
       a.hist_range = w.range;

@@ -362,8 +362,8 @@ hipError_t launch_convolve(const uint32_t *counts, int nbins, const double *rang
 
 hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range, double tau0,
                               double omega, int mode, double *v, double *wake_par,
-                              hipStream_t st) {
-  return launch_conv<true>(dip, nbins, 1, range, tau0, omega, mode, v, wake_par, nullptr, 0, st);
+                              hipStream_t st, uint32_t *zbuf, int zn) {
+  return launch_conv<true>(dip, nbins, 1, range, tau0, omega, mode, v, wake_par, zbuf, zn, st);
 }
 
 // ------------------------------------------------------------------ wake kick

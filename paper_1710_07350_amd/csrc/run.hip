@@ -165,6 +165,18 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t step = kMom ? 0 : nthr * kP;
   const int64_t ntot = a.n_total;
+  // the next wake's histogram, binned here when the run changes neither s
+  // nor the alive set (its range is the last histogram's, exact)
+  extern __shared__ uint32_t hsub[];
+  const bool hist = !kMom && a.hist_out != nullptr;
+  double hmn = 0.0, hinv = 0.0;
+  if (hist) {
+    for (int j = threadIdx.x; j < a.hist_nbins; j += kBlock) hsub[j] = 0u;
+    hmn = a.hist_range[0];
+    const double width = a.hist_range[1] - hmn;
+    hinv = width > 0.0 ? static_cast<double>(a.hist_nbins) / width : 0.0;
+    __syncthreads();
+  }
 
   for (int64_t it = 0, base = first; kMom ? (it < 1) : (base < ntot); ++it, base += step) {
     double z[kP][6];
@@ -244,10 +256,22 @@ __global__ __launch_bounds__(kBlock) void k_run(const RunArgs a) {
       if (alive[q]) {
         smin = fmin(smin, z[q][4]);
         smax = fmax(smax, z[q][4]);
+        if (hist) {
+          const double f = (z[q][4] - hmn) * hinv;
+          if (f >= 0.0) atomicAdd(hsub + min(static_cast<int>(f), a.hist_nbins - 1), 1u);
+        }
       }
     }
     if constexpr (!kMom) {
       if (base + nthr * kP >= n) break;  // nothing alive further on
+    }
+  }
+  if (hist) {
+    __syncthreads();
+    uint32_t *out = a.hist_out + (blockIdx.x % kHistCopies) * a.hist_nbins;
+    for (int j = threadIdx.x; j < a.hist_nbins; j += kBlock) {
+      const uint32_t c = hsub[j];
+      if (c != 0u) atomicAdd(out + j, c);
     }
   }
   if (a.mm_part != nullptr) {
@@ -266,8 +290,8 @@ constexpr bool longit_ok(uint32_t f) { return (f & ~(F_RF | F_WAKE)) == 0; }
 
 template <uint32_t kFeat, bool kLong, bool kNT>
 void launch_ppt_nt(const RunArgs &a, int grid, hipStream_t st) {
-  // a run-binned histogram keeps its counts in LDS (two-coordinate runs only)
-  const size_t lds = kLong && a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
+  // a run-binned histogram keeps its counts in LDS
+  const size_t lds = a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
   switch (a.ppt) {
     case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
     case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
@@ -301,10 +325,11 @@ void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
     launch_ppt<kFeat, false>(a, grid, st);
   } else {
     // heavy runs: one or two particles per thread
+    const size_t lds = a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
     if (a.ppt >= 2)
-      hipLaunchKernelGGL((k_run<kFeat, false, 2, false>), dim3(grid), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_run<kFeat, false, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
     else
-      hipLaunchKernelGGL((k_run<kFeat, false, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
+      hipLaunchKernelGGL((k_run<kFeat, false, 1, false>), dim3(grid), dim3(kBlock), lds, st, a);
   }
 }
 

@@ -174,7 +174,8 @@ hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_t
                             const double *y = nullptr, int64_t *dip = nullptr);
 // transverse: v[2][nbins] from dip[2][nbins]
 hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range, double tau0,
-                              double omega, int mode, double *v, double *wake_par, hipStream_t st);
+                              double omega, int mode, double *v, double *wake_par, hipStream_t st,
+                              uint32_t *zbuf = nullptr, int zn = 0);
 hipError_t launch_trwake_kick(double *const z[6], const int64_t *n_alive, int64_t n_total,
                               const double *v, const double *wake_par, int nbins, double kfac,
                               hipStream_t st);
