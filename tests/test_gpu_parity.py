@@ -193,6 +193,21 @@ def test_run_binned_histograms_mixed_bins(torch):
     assert np.array_equal(f32[0]["z"], f32[1]["z"]) and np.array_equal(f32[0]["id"], f32[1]["id"])
 
 
+def test_run_binned_histograms_with_random_kicks(torch):
+    """A random energy kick moves neither s nor the alive set: runs holding
+    one still bin the next histogram, bit-exact with the oracle (Philox)."""
+    wk = dict(wake_A=1e14, wake_tau0=10e-12, wake_omega=2 * math.pi * 50e9, charge=1e-9,
+              nbins=512)
+    rf = dict(volt=20e6, phase=math.radians(-20), freq=1.3e9)
+    lat = [Element("RFCA", **rf), Element("WAKE", **wk), Element("RADKICK", sigma=1e-4),
+           Element("RFCA", **rf), Element("WAKE", **wk), Element("RADKICK", sigma=1e-4),
+           Element("WAKE", **wk), Element("MAP2", coef=inputs.chicane_coef())]
+    d = inputs.gaussian_beam(40_000, seed=4, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, seed=11, wake_mode=B.WAKE_FP64)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV, seed=11)
+    assert_bit_exact(g, r)
+
+
 @pytest.mark.parametrize("n", [100_000, 4_000_000])
 def test_bunch_compressor_fp32_mfma_within_bound(torch, n):
     lat = inputs.bc_lattice()
