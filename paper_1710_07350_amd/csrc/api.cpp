@@ -752,10 +752,11 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   // alive set packed, or the call ends.  The final layout does not depend on
   // when compaction runs.
   bool dirty = false;
-  // A run that changes neither s nor the alive set (RF kicks, wake kicks and
-  // markers, no apertures) bins the histogram of a longitudinal wake that
-  // follows it, over the range of the last histogram: nothing since has
-  // moved s or lost a particle, so that range is the beam's (exactly).
+  // A run that changes neither s nor the alive set (RF, wake, transverse-wake
+  // and random energy kicks, markers; no apertures) bins the histogram of a
+  // longitudinal wake that follows it, over the range of the last histogram:
+  // nothing since has moved s or lost a particle, so that range is the
+  // beam's (exactly).
   // range_ok: w.range describes the current beam; fused_buf: the buffer the
   // previous run binned the coming wake's histogram into (-1: none); hnext:
   // the buffer the next such run bins into (the two alternate, so a
