@@ -15,13 +15,15 @@
  *   decay with the distance travelled.
  * Layout: structure of arrays (Sec. 2: SoA for coalesced access), one
  *   contiguous binary64 array per coordinate.  Device pointers only.
- * Alive set: particle i is alive iff i < *n_alive.  Every call that can lose
- *   particles reorders the arrays before it returns so that this holds
- *   (alive ones first, in their previous order; lost ones after, latest loss
- *   first) -- the role of the paper's particle-loss algorithm (Sec. 2.5),
- *   made stable.  lost_at[i] = -1 for alive particles, else
- *   (pass << 32) | element_index of the element at whose exit the particle
- *   failed the aperture; its coordinates are frozen at that exit.
+ * Alive set: particle i is alive iff i < *n_alive (a value above n_total
+ *   counts as n_total, and a compaction stores the clamped count back).
+ *   Every call that can lose particles reorders the arrays before it returns
+ *   so that this holds (alive ones first, in their previous order; lost
+ *   ones after, latest loss first) -- the role of the paper's
+ *   particle-loss algorithm (Sec. 2.5), made stable.  lost_at[i] = -1 for
+ *   alive particles, else (pass << 32) | element_index of the element at
+ *   whose exit the particle failed the aperture; its coordinates are frozen
+ *   at that exit.
  * Ownership: beams, outputs and workspaces are allocated by the caller
  *   (e.g. as torch tensors); the library never frees them.  A lattice handle
  *   owns a device copy of its element records.

@@ -13,9 +13,9 @@ constexpr double kCLight = 299792458.0;
 // ------------------------------------------------------------------ range
 __global__ __launch_bounds__(kBlock) void k_minmax(const double *__restrict__ s,
                                                    const int64_t *__restrict__ n_alive,
-                                                   double *__restrict__ part, uint32_t *zero_buf,
-                                                   int zero_n) {
-  const int64_t n = *n_alive;
+                                                   int64_t n_total, double *__restrict__ part,
+                                                   uint32_t *zero_buf, int zero_n) {
+  const int64_t n = min(*n_alive, n_total);
   if (zero_buf != nullptr && blockIdx.x == 0)
     for (int i = threadIdx.x; i < zero_n; i += kBlock) zero_buf[i] = 0u;
   double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
@@ -34,8 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const double *__restrict__ s,
 
 hipError_t launch_minmax(const double *s, const int64_t *n_alive, int64_t n_total, double *mm_part,
                          int grid, uint32_t *zero_buf, int zero_n, hipStream_t st) {
-  hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(kBlock), 0, st, s, n_alive, mm_part, zero_buf,
-                     zero_n);
+  hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(kBlock), 0, st, s, n_alive, n_total, mm_part,
+                     zero_buf, zero_n);
   return hipGetLastError();
 }
 
@@ -370,10 +370,10 @@ hipError_t launch_convolve_tr(const int64_t *dip, int nbins, const double *range
 __global__ __launch_bounds__(kBlock) void k_wake_kick(const double *__restrict__ s,
                                                       double *__restrict__ dp,
                                                       const int64_t *__restrict__ n_alive,
-                                                      const double *__restrict__ v,
+                                                      int64_t n_total, const double *__restrict__ v,
                                                       const double *__restrict__ wake_par,
                                                       int nbins, double kfac) {
-  const int64_t n = *n_alive;
+  const int64_t n = min(*n_alive, n_total);
   const double smin = wake_par[0], inv = wake_par[1];
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -387,8 +387,8 @@ hipError_t launch_wake_kick(double *s, double *dp, const int64_t *n_alive, int64
                             hipStream_t st) {
   const int64_t want = nblocks(n_total);
   const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxRunGrid ? kMaxRunGrid : want));
-  hipLaunchKernelGGL(k_wake_kick, dim3(grid), dim3(kBlock), 0, st, s, dp, n_alive, v, wake_par,
-                     nbins, kfac);
+  hipLaunchKernelGGL(k_wake_kick, dim3(grid), dim3(kBlock), 0, st, s, dp, n_alive, n_total, v,
+                     wake_par, nbins, kfac);
   return hipGetLastError();
 }
 
@@ -398,10 +398,11 @@ __global__ __launch_bounds__(kBlock) void k_trwake_kick(double *__restrict__ xp,
                                                         const double *__restrict__ s,
                                                         const double *__restrict__ dp,
                                                         const int64_t *__restrict__ n_alive,
+                                                        int64_t n_total,
                                                         const double *__restrict__ v,
                                                         const double *__restrict__ wake_par,
                                                         int nbins, double kfac) {
-  const int64_t n = *n_alive;
+  const int64_t n = min(*n_alive, n_total);
   const double smin = wake_par[0], inv = wake_par[1];
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -419,7 +420,7 @@ hipError_t launch_trwake_kick(double *const z[6], const int64_t *n_alive, int64_
   const int64_t want = nblocks(n_total);
   const int grid = static_cast<int>(want < 1 ? 1 : (want > kMaxRunGrid ? kMaxRunGrid : want));
   hipLaunchKernelGGL(k_trwake_kick, dim3(grid), dim3(kBlock), 0, st, z[1], z[3], z[4], z[5],
-                     n_alive, v, wake_par, nbins, kfac);
+                     n_alive, n_total, v, wake_par, nbins, kfac);
   return hipGetLastError();
 }
 
@@ -432,9 +433,10 @@ struct Z6 {
 };
 
 __global__ __launch_bounds__(kBlock) void k_mom_partial(Z6 z, const int64_t *__restrict__ n_alive,
+                                                        int64_t n_total,
                                                         const double *__restrict__ shift,
                                                         double *__restrict__ part) {
-  const int64_t n = *n_alive;
+  const int64_t n = min(*n_alive, n_total);
   double c[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) c[k] = shift ? shift[k] : 0.0;
@@ -463,7 +465,8 @@ hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_
                               const double *shift, double *part, int grid, hipStream_t st) {
   Z6 zz;
   for (int k = 0; k < 6; ++k) zz.p[k] = z[k];
-  hipLaunchKernelGGL(k_mom_partial, dim3(grid), dim3(kBlock), 0, st, zz, n_alive, shift, part);
+  hipLaunchKernelGGL(k_mom_partial, dim3(grid), dim3(kBlock), 0, st, zz, n_alive, n_total, shift,
+                     part);
   return hipGetLastError();
 }
 

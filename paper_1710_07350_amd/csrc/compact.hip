@@ -74,6 +74,22 @@ __device__ __forceinline__ int64_t tile_slot(int r) {
 }
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << (threadIdx.x & 63)) - 1ull; }
 
+// The tile's loss records (-1 at and beyond n <= n_total), every load issued
+// before the first is used: a ballot on each record as it arrives would wait
+// for the loads one by one.  Slots at and beyond n read slot 0 (present in
+// any launched grid) and drop it, so no branch separates the loads.
+__device__ __forceinline__ void load_records(const int64_t *__restrict__ lost_at, int64_t n,
+                                             int64_t (&rec)[kCmpRounds]) {
+  int64_t v[kCmpRounds];
+#pragma unroll
+  for (int r = 0; r < kCmpRounds; ++r) {
+    const int64_t i = tile_slot(r);
+    v[r] = lost_at[i < n ? i : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kCmpRounds; ++r) rec[r] = tile_slot(r) < n ? v[r] : -1;
+}
+
 // Exclusive offsets of the four waves' totals (in wave order), for two
 // counters at once; returns the block totals through tot.
 __device__ __forceinline__ void wave_offsets(int a, int b, int &oa, int &ob, int &ta, int &tb) {
@@ -99,14 +115,10 @@ __device__ __forceinline__ void wave_offsets(int a, int b, int &oa, int &ob, int
 
 __global__ __launch_bounds__(kBlock) void k_cmp_count(const int64_t *__restrict__ lost_at,
                                                       const int64_t *__restrict__ n_alive,
-                                                      int64_t *__restrict__ blk) {
-  const int64_t n = *n_alive;
+                                                      int64_t n_total, int64_t *__restrict__ blk) {
+  const int64_t n = min(*n_alive, n_total);
   int64_t rec[kCmpRounds];
-#pragma unroll
-  for (int r = 0; r < kCmpRounds; ++r) {
-    const int64_t i = tile_slot(r);
-    rec[r] = i < n ? lost_at[i] : -1;
-  }
+  load_records(lost_at, n, rec);
   int na = 0, nl = 0;  // per wave
   int64_t m[5] = {kI64Max, kI64Max, kI64Max, kI64Max, kI64Max};
 #pragma unroll
@@ -167,7 +179,8 @@ __device__ __forceinline__ int64_t block_scan_i64(int64_t v, int64_t &total) {
 
 __global__ __launch_bounds__(kScanThreads) void k_cmp_scan(int64_t *__restrict__ blk, int64_t nblk,
                                                            int64_t *__restrict__ hdr,
-                                                           int64_t *__restrict__ n_alive) {
+                                                           int64_t *__restrict__ n_alive,
+                                                           int64_t n_total) {
   const int64_t chunk = (nblk + kScanThreads - 1) / kScanThreads;
   const int64_t b0 = threadIdx.x * chunk;
   const int64_t b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
@@ -191,7 +204,7 @@ __global__ __launch_bounds__(kScanThreads) void k_cmp_scan(int64_t *__restrict__
   }
   block_min_i64<5, kScanThreads>(m);
   if (threadIdx.x == 0) {
-    const int64_t n_old = *n_alive;
+    const int64_t n_old = min(*n_alive, n_total);
     hdr[H_NOLD] = n_old;
     hdr[H_NNEW] = n_old - tl;
     hdr[H_NLOST] = tl;
@@ -222,13 +235,10 @@ __global__ __launch_bounds__(kBlock) void k_cmp_gather(const int64_t *__restrict
   if (hdr[H_NLOST] == 0) return;
   const int64_t n = hdr[H_NOLD];
   int64_t rec[kCmpRounds];
+  load_records(lost_at, n, rec);
   int cnt = 0;
 #pragma unroll
-  for (int r = 0; r < kCmpRounds; ++r) {
-    const int64_t i = tile_slot(r);
-    rec[r] = i < n ? lost_at[i] : -1;
-    cnt += __popcll(__ballot(rec[r] >= 0));
-  }
+  for (int r = 0; r < kCmpRounds; ++r) cnt += __popcll(__ballot(rec[r] >= 0));
   int off, o2, tot, t2;
   wave_offsets(cnt, 0, off, o2, tot, t2);
   if (tot == 0) return;
@@ -370,12 +380,13 @@ __global__ __launch_bounds__(kBlock) void k_cmp_scatter(BeamPtrs beam, BeamPtrs 
   const int64_t nl = hdr[H_NLOST];
   if (nl == 0) return;
   const int64_t n_old = hdr[H_NOLD], n_new = hdr[H_NNEW], lo = hdr[H_LO];
+  int64_t rec[kCmpRounds];
+  load_records(beam.lost_at, n_old, rec);
   bool alive[kCmpRounds];
   int cnt = 0;
 #pragma unroll
   for (int r = 0; r < kCmpRounds; ++r) {
-    const int64_t i = tile_slot(r);
-    alive[r] = i < n_old && beam.lost_at[i] < 0;
+    alive[r] = tile_slot(r) < n_old && rec[r] < 0;
     cnt += __popcll(__ballot(alive[r]));
   }
   int off, o2, tot, t2;
@@ -574,9 +585,10 @@ hipError_t launch_compact(double *const z[6], uint32_t *id, int64_t *lost_at, in
   beam.lost_at = lost_at;
   stage.id = w.tid;
   stage.lost_at = w.tlost;
-  hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, w.cmp_blk);
+  hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, n_total,
+                     w.cmp_blk);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(kScanThreads), 0, st, w.cmp_blk, nb, w.cmp_hdr,
-                     n_alive);
+                     n_alive, n_total);
   hipLaunchKernelGGL(k_cmp_gather, dim3(grid), dim3(kBlock), 0, st, lost_at, w.cmp_blk, w.cmp_hdr,
                      w.key_a, w.pos_a);
   hipLaunchKernelGGL(k_cmp_sort, dim3(1), dim3(1024), 0, st, w.cmp_hdr, w.key_a, w.pos_a, w.key_b,
@@ -611,11 +623,11 @@ __global__ __launch_bounds__(kBlock) void k_swap_list(const int64_t *__restrict_
   if (hdr[H_NLOST] == 0) return;
   const int64_t n_old = hdr[H_NOLD], n_new = hdr[H_NNEW];
   int64_t rec[kCmpRounds];
+  load_records(lost_at, n_old, rec);
   int cl = 0, ca = 0, ch = 0;
 #pragma unroll
   for (int r = 0; r < kCmpRounds; ++r) {
     const int64_t i = tile_slot(r);
-    rec[r] = i < n_old ? lost_at[i] : -1;
     cl += __popcll(__ballot(rec[r] >= 0));
     ca += __popcll(__ballot(i < n_old && rec[r] < 0));
     ch += __popcll(__ballot(rec[r] >= 0 && i < n_new));
@@ -754,9 +766,10 @@ hipError_t launch_compact_variant(int mode, double *const z[6], uint32_t *id, in
   beam.lost_at = lost_at;
   stage.id = w.tid;
   stage.lost_at = w.tlost;
-  hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, w.cmp_blk);
+  hipLaunchKernelGGL(k_cmp_count, dim3(grid), dim3(kBlock), 0, st, lost_at, n_alive, n_total,
+                     w.cmp_blk);
   hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(kScanThreads), 0, st, w.cmp_blk, nb, w.cmp_hdr,
-                     n_alive);
+                     n_alive, n_total);
   if (mode == TRK_COMPACT_SWAP) {
     hipLaunchKernelGGL(k_swap_list, dim3(grid), dim3(kBlock), 0, st, lost_at, w.cmp_blk, w.cmp_hdr,
                        w.pos_a, w.pos_b);

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_gate_count(const BeamPtrs6 b, const 
                                                        int64_t n_total, const SurrDev c,
                                                        uint8_t *__restrict__ flags, int64_t *__restrict__ blk) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t na = *n_alive;
+  const int64_t na = min(*n_alive, n_total);
   int f = 0, rej = 0;
   if (i < n_total) {
     if (i < na) {
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_gate_split(const uint8_t *__restrict
                                                        int64_t n_total, const int64_t *__restrict__ blk,
                                                        uint32_t *__restrict__ adm, uint32_t *__restrict__ rej) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t na = *n_alive;
+  const int64_t na = min(*n_alive, n_total);
   const int f = (i < n_total) ? flags[i] : 0;
   const int r = (i < na && f == 0) ? 1 : 0;
   int ta, tr;

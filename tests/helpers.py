@@ -21,9 +21,11 @@ def rel_err(a, b, scale=COORD_SCALE):
     return float(np.nanmax(e)) if e.size else 0.0
 
 
-def run_gpu(lat, d, passes, p_ref=1e9, seed=0, moments=False, **kw):
+def run_gpu(lat, d, passes, p_ref=1e9, seed=0, moments=False, n_alive=None, **kw):
     import torch
     beam = B.Beam.from_inputs(d)
+    if n_alive is not None:
+        beam.n_alive.fill_(n_alive)
     ws = B.Workspace(beam.n)
     L = B.Lattice(lat)
     mom = torch.zeros((max(passes, 1), 28), dtype=torch.float64, device="cuda") if moments else None

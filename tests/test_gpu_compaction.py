@@ -63,3 +63,19 @@ def test_compaction_variants_repeat_on_a_compacted_beam(torch):
         twice = beam.host()
         for k in ("z", "id", "lost_at", "n_alive"):
             assert np.array_equal(once[k], twice[k])
+
+
+@pytest.mark.parametrize("mode", [B.COMPACT_STABLE, B.COMPACT_SWAP, B.COMPACT_SORT])
+def test_alive_count_above_the_beam_counts_as_the_beam(torch, mode):
+    """*n_alive beyond n_total acts as n_total (no slot past the arrays is
+    read) and the clamped count minus the losses is stored back."""
+    n = 4096 * 3 + 100                           # ragged last tile
+    d = lossy(n, 0.05, 11, 0)
+    over = B.Beam(d["z"], d["id"], d["lost_at"], n_alive=n + 5000)
+    exact = B.Beam(d["z"], d["id"], d["lost_at"], n_alive=n)
+    for b in (over, exact):
+        B.compact_lost(b, B.Workspace(b.n), mode=mode)
+    g, e = over.host(), exact.host()
+    assert g["n_alive"] == e["n_alive"] < n
+    for k in ("z", "id", "lost_at"):
+        assert np.array_equal(g[k], e[k])

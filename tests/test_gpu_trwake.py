@@ -13,7 +13,7 @@ from paper_1710_07350_amd import binding as B
 from paper_1710_07350_amd import inputs
 from paper_1710_07350_amd.inputs import Element
 
-from helpers import assert_bit_exact, run_gpu, run_oracle
+from helpers import assert_bit_exact, moments_close, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +135,25 @@ def test_trwake_after_losses(torch):
         r = run_oracle(lat, d, 3)
         assert 0 < r["n_alive"] < 20_000
         assert_bit_exact(g, r)
+
+
+def test_alive_count_above_the_beam(torch):
+    """An alive count beyond the arrays acts as their length in every kernel
+    that reads it (fused runs, extent, histograms, wake kicks, losses,
+    moments): bit-exact with the oracle on the whole beam."""
+    a = dict(aperture="RECT", ax=1.5e-3, ay=1.5e-3)
+    lat = [Element("EDRIFT", L=2.0, **a), Element("QUAD", L=0.2, k=1.2, **a),
+           Element("WAKE", wake_A=3e16, wake_tau0=TAU0, wake_omega=OMEGA, charge=1e-9, nbins=96),
+           Element("TRWAKE", wake_A=3e16, wake_tau0=TAU0, wake_omega=OMEGA, charge=1e-9, nbins=128),
+           Element("EDRIFT", L=1.0, **a)]
+    n = 4096 * 5 + 77
+    d = inputs.gaussian_beam(n, seed=19, sigmas=(2e-3, 2e-4, 2e-3, 2e-4, 1e-3, 1e-3))
+    r = run_oracle(lat, d, 2, moments=True)
+    assert 0 < r["n_alive"] < n
+    for kw in (dict(), dict(max_elems_per_launch=1)):
+        g = run_gpu(lat, d, 2, wake_mode=B.WAKE_FP64, moments=True, n_alive=n + 9000, **kw)
+        assert_bit_exact(g, r)
+        moments_close(g["moments"], r["moments"])
 
 
 @pytest.mark.parametrize("n", [400_000, 4_000_000])
