@@ -167,7 +167,9 @@ size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total);
  * consecutive elements are fused into one kernel (coordinates loaded once,
  * kept in registers, stored once); TRK_WAKE and TRK_TRWAKE split runs.  Results do not
  * depend on the fusion depth.  Returns after enqueuing; the beam is
- * reordered (alive set first) when the last kernel completes. */
+ * reordered (alive set first) when the last kernel completes.  With no
+ * passes, no elements or n_total = 0 nothing is enqueued and opts.moments
+ * is left as it was. */
 int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes, const trk_opts *opts,
               void *workspace, size_t workspace_bytes, void *stream);
 

@@ -71,6 +71,29 @@ def test_every_particle_lost(torch):
     assert np.isnan(g["moments"][-1, 1:]).all() and g["moments"][-1, 0] == 0
 
 
+def test_zero_slot_beam_is_a_no_op(torch):
+    """n_total = 0 with valid device pointers: tracking (moments requested)
+    and the three reorderings enqueue nothing; the moments call reports
+    n = 0 with undefined (NaN) means and second moments."""
+    d = inputs.gaussian_beam(1, seed=1)
+    beam = B.Beam.from_inputs(d)
+    before = beam.host()
+    ws = B.Workspace(1)
+    lat = B.Lattice(inputs.fodo_lattice(ncells=2, aper=1e-4))
+    mom = torch.full((3, 28), 7.0, dtype=torch.float64, device="cuda")
+    beam.n = 0
+    B.track(beam, lat, 3, ws, moments=mom)
+    for mode in (B.COMPACT_STABLE, B.COMPACT_SWAP, B.COMPACT_SORT):
+        B.compact_lost(beam, ws, mode=mode)
+    m = B.moments(beam, ws).cpu().numpy()
+    beam.n = 1
+    after = beam.host()
+    for k in ("z", "id", "lost_at", "n_alive"):
+        assert np.array_equal(before[k], after[k])
+    assert (mom.cpu().numpy() == 7.0).all()
+    assert m[0] == 0 and np.isnan(m[1:]).all()
+
+
 def test_first_pass_offset_and_markers(torch):
     lat = inputs.fodo_lattice(ncells=2) + [Element("MARKER", aperture="ELLIPSE", ax=4e-3, ay=3e-3)]
     d = inputs.gaussian_beam(4000, seed=9, sigmas=WIDE)
@@ -191,6 +214,23 @@ def test_run_binned_histograms_mixed_bins(torch):
     f32 = [run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA, run_hist=h)
            for h in (0, -1)]
     assert np.array_equal(f32[0]["z"], f32[1]["z"]) and np.array_equal(f32[0]["id"], f32[1]["id"])
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(run_ppt=2, run_blocks=5)])
+def test_run_binned_histograms_at_the_bin_limits(torch, kw):
+    """Run-binned histograms at the largest bin count a wake may have (the
+    run's LDS sub-histogram at its maximum) and at the smallest, on a ragged
+    beam: bit-exact with the oracle."""
+    wk = dict(wake_A=1e14, wake_tau0=10e-12, wake_omega=2 * math.pi * 50e9, charge=1e-9)
+    rf = dict(volt=20e6, phase=math.radians(-20), freq=1.3e9)
+    lat = [Element("RFCA", **rf), Element("WAKE", nbins=B.MAX_BINS, **wk), Element("RFCA", **rf),
+           Element("WAKE", nbins=B.MAX_BINS, **wk), Element("RFCA", **rf),
+           Element("WAKE", nbins=2, **wk), Element("RFCA", **rf), Element("WAKE", nbins=2, **wk),
+           Element("MAP2", coef=inputs.chicane_coef())]
+    d = inputs.gaussian_beam(30_001, seed=6, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, **kw)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
 
 
 def test_run_binned_histograms_with_random_kicks(torch):
