@@ -445,11 +445,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const int64_t *__restrict__
   __syncthreads();
   const uint64_t *src = (pass & 1) ? kb : ka;
   const int shift = 8 * pass;
+  // every key load issued before the first atomic (slot 0 stands in past nl)
+  uint64_t key[kCmpRounds];
 #pragma unroll
   for (int r = 0; r < kCmpRounds; ++r) {
     const int64_t j = tile_slot(r);
-    if (j < nl) atomicAdd(&hist[(src[j] >> shift) & 255u], 1u);
+    key[r] = src[j < nl ? j : 0];
   }
+#pragma unroll
+  for (int r = 0; r < kCmpRounds; ++r)
+    if (tile_slot(r) < nl) atomicAdd(&hist[(key[r] >> shift) & 255u], 1u);
   __syncthreads();
   cnt[static_cast<int64_t>(threadIdx.x) * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
@@ -506,9 +511,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(int64_t *__restrict__ hdr
 #pragma unroll
   for (int r = 0; r < kCmpRounds; ++r) {
     const int64_t j = tile_slot(r);
-    const bool valid = j < nl;
-    key[r] = valid ? sk[j] : 0ull;
-    val[r] = valid ? sp[j] : 0u;
+    key[r] = sk[j < nl ? j : 0];  // all loads before the first ballot
+    val[r] = sp[j < nl ? j : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kCmpRounds; ++r) {
+    const bool valid = tile_slot(r) < nl;
+    if (!valid) key[r] = 0ull;
     const uint32_t dg = static_cast<uint32_t>((key[r] >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll
