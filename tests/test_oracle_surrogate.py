@@ -288,3 +288,188 @@ def test_gate_admits_only_survivors(orc):
     z2 = np.zeros((6, 3))
     z2[5] = [1.01 * HW[5], -1.01 * HW[5], 0.1 * HW[5]]
     assert list(S.gate(z2, g)) == [False, False, True]
+
+
+# ---------------------------------------------------------------- sampler box
+def _gate_and_widths(orc, margin=0.5):
+    C, R = S.linear_map(orc, section(), HW, H_REL)
+    g = S.gate_constants(R, partial_maps(orc), HW, margin, 10e-3, 5e-3)
+    return g, S.sample_widths(g, 10e-3, 5e-3)
+
+
+def _to_box_edge(v, hw):
+    """Scale each ray (column) so that its largest |v_k| / hw_k is 1: at
+    t = 1 it touches the training box, beyond it the gate refuses."""
+    return v / (np.abs(v) / np.asarray(hw)[:, None]).max(axis=0)
+
+
+def _boundary(g, v, iters=70):
+    """Outermost admitted point along each ray t v, 0 < t <= 1, for rays
+    scaled to the box edge: the admitted set is star-shaped about the origin
+    (the box is, and the amplitudes sqrt(J) and |delta| scale linearly with
+    t), so bisection finds its edge."""
+    v = _to_box_edge(v, g["hw"])
+    lo = np.zeros(v.shape[1])
+    hi = np.full(v.shape[1], 1.0 + 1e-9)
+    assert not S.gate(v * hi, g).any()
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        ok = S.gate(v * mid, g)
+        lo = np.where(ok, mid, lo)
+        hi = np.where(ok, hi, mid)
+    return v * lo
+
+
+def _extremal_rays(g):
+    """Rays through the points of the Courant--Snyder ellipses where one
+    coordinate is extreme: on gamma u^2 + 2 alpha u u' + beta u'^2 = J the
+    largest u is sqrt(J beta) at u' = -alpha sqrt(J/beta), the largest u' is
+    sqrt(J gamma) at u = -alpha sqrt(J/gamma); the pure dispersion ray
+    (eta, eta', 0, 0, 0, 1) has no betatron amplitude at all.  Mixtures of
+    the x-extreme betatron ray and the dispersion ray (each scaled to one
+    unit of the gate's x amplitude) cover the shared budget."""
+    bx, gx, ax = g["bx"], g["gx"], g["ax2"] / 2.0
+    by, gy, ay = g["by"], g["gy"], g["ay2"] / 2.0
+    bet_x = np.array([math.sqrt(bx), -ax / math.sqrt(bx), 0, 0, 0, 0]) / math.sqrt(g["bhx"])
+    bet_xp = np.array([-ax / math.sqrt(gx), math.sqrt(gx), 0, 0, 0, 0]) / math.sqrt(g["bhx"])
+    disp = np.array([g["eta"], g["etap"], 0, 0, 0, 1.0]) / g["eh"]
+    rays = [np.array([0, 0, math.sqrt(by), -ay / math.sqrt(by), 0, 0]),
+            np.array([0, 0, -ay / math.sqrt(gy), math.sqrt(gy), 0, 0]), disp]
+    sx = 1.0 if g["eta"] >= 0 else -1.0
+    sxp = 1.0 if g["etap"] >= 0 else -1.0
+    for c in np.linspace(0.0, 1.0, 41):
+        rays.append((1 - c) * bet_x + c * sx * disp)
+        rays.append((1 - c) * bet_xp + c * sxp * disp)
+    rays += [-r for r in rays]
+    return np.array(rays, dtype=float).T
+
+
+def test_sampler_box_contains_every_admitted_point(orc):
+    """sample_widths bounds every coordinate of every admitted point: points
+    on the edge of the admitted set (bisection along random rays and along the
+    rays of the extremal ellipse points), and admitted points of a uniform box
+    wider than the sampler's, all lie within the half widths."""
+    g, sw = _gate_and_widths(orc)
+    rng = np.random.default_rng(31)
+    n = 40000
+    v = rng.standard_normal((6, n))
+    v[4] = 0.0
+    v *= HW[:, None]
+    # rays weighted towards a few coordinates at a time as well
+    v2 = rng.standard_normal((6, n)) * (rng.random((6, n)) < 0.4) * HW[:, None]
+    v2[4] = 0.0
+    v2 = v2[:, np.abs(v2).sum(0) > 0]
+    edge = _boundary(g, np.concatenate([v, v2, _extremal_rays(g)], axis=1))
+    assert S.gate(edge, g).all()
+    for k in (0, 1, 2, 3, 5):
+        assert (np.abs(edge[k]) <= sw[k]).all(), (k, np.abs(edge[k]).max(), sw[k])
+    wide = np.minimum(1.5 * sw, HW)
+    wide[4] = HW[4]
+    box = inputs.uniform_box_beam(400000, seed=32, half_widths=wide)["z"]
+    adm = S.gate(box, g)
+    assert adm.sum() > 2000
+    for k in (0, 1, 2, 3, 5):
+        assert (np.abs(box[k, adm]) <= sw[k]).all()
+
+
+def test_sampler_box_is_not_loose(orc):
+    """The half widths are reached.  With the training box widened tenfold
+    (so that only the amplitude bound limits), the edge points of the
+    extremal rays reach the uncapped widths of y, y' and delta (the bound is
+    exact there, up to the 1e-6 padding), and those of x and x' at least
+    half-way (their bound adds the betatron and the dispersion extremes,
+    which the gate makes share one amplitude budget)."""
+    g, sw = _gate_and_widths(orc)
+    gw = dict(g, hw=tuple(10.0 * HW))
+    sww = S.sample_widths(gw, 10e-3, 5e-3)
+    assert (sww[[0, 1, 2, 3, 5]] < 10.0 * HW[[0, 1, 2, 3, 5]]).all()
+    np.testing.assert_array_equal(np.minimum(sww, HW), sw)
+    edge = _boundary(gw, _extremal_rays(gw))
+    reach = np.abs(edge).max(axis=1) / sww
+    assert (reach[[0, 1, 2, 3, 5]] <= 1.0).all()
+    for k in (2, 3, 5):
+        assert reach[k] > 1 - 1e-5, (k, reach[k])
+    for k in (0, 1):
+        assert reach[k] > 0.5, (k, reach[k])
+    # a larger margin shrinks every width
+    g2 = S.gate_constants(S.linear_map(orc, section(), HW, H_REL)[1], partial_maps(orc),
+                          10.0 * HW, 0.7, 10e-3, 5e-3)
+    sw2 = S.sample_widths(g2, 10e-3, 5e-3)
+    assert (sw2[[0, 1, 2, 3, 5]] < sww[[0, 1, 2, 3, 5]]).all()
+
+
+def _synthetic_gate(rng, g0):
+    """Gate constants of an arbitrary lattice position: random Twiss
+    parameters (beta gamma - alpha^2 = 1), dispersion, and maxima over the
+    section at or above the entrance values, as gate_constants produces."""
+    g = dict(g0, hw=tuple(10.0 * HW))
+    for pl in ("x", "y"):
+        b = rng.uniform(1.0, 20.0)
+        a = rng.uniform(-2.0, 2.0)
+        g["b" + pl] = b
+        g["a" + pl + "2"] = 2.0 * a
+        g["g" + pl] = (1.0 + a * a) / b
+        g["bh" + pl] = b * rng.uniform(1.0, 4.0)
+    g["eta"] = rng.uniform(-3.0, 3.0)
+    g["etap"] = rng.uniform(-0.5, 0.5)
+    g["eh"] = abs(g["eta"]) * rng.uniform(1.0, 3.0) + 0.1
+    return g
+
+
+def test_sampler_box_contains_admitted_points_of_any_lattice(orc):
+    """Containment and reach for random gate constants (the section's own
+    constants leave the dispersion term of x inside the cap of the box)."""
+    g0, _ = _gate_and_widths(orc)
+    rng = np.random.default_rng(33)
+    for _ in range(12):
+        g = _synthetic_gate(rng, g0)
+        sw = S.sample_widths(g, 10e-3, 5e-3)
+        v = rng.standard_normal((6, 4000)) * HW[:, None]
+        v[4] = 0.0
+        edge = _boundary(g, np.concatenate([v, _extremal_rays(g)], axis=1))
+        reach = np.abs(edge).max(axis=1) / sw
+        assert (reach[[0, 1, 2, 3, 5]] <= 1.0).all(), reach
+        assert (reach[[2, 3, 5]] > 1 - 1e-5).all(), reach
+        assert (reach[[0, 1]] > 0.5).all(), reach
+
+
+class _Words:
+    """Stand-in generator returning fixed words, to pin the word -> uniform
+    -> coordinate map of the sampler."""
+
+    def __init__(self, w):
+        self.w = w
+
+    def philox4x32_10(self, ctr, key):
+        return list(self.w[:4]) if ctr[3] == 0 else list(self.w[4:])
+
+
+def test_sampler_draw_maps_words_to_the_open_box():
+    sw = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    lo = S.draw(_Words([0] * 8), sw, 0, 0)
+    hi = S.draw(_Words([0xFFFFFFFF] * 8), sw, 0, 0)
+    mid = S.draw(_Words([0x7FFFFFFF] * 8), sw, 0, 0)
+    q = 2.0 ** -32
+    np.testing.assert_array_equal(lo, -(1.0 - q) * sw)
+    np.testing.assert_array_equal(hi, (1.0 - q) * sw)
+    np.testing.assert_array_equal(mid, -q * sw * 0.0 + (2.0 * (0x7FFFFFFF + 0.5) * q - 1.0) * sw)
+    # word k of the two blocks feeds coordinate k
+    w = list(range(1000, 1008))
+    z = S.draw(_Words(w), sw, 0, 0)
+    np.testing.assert_array_equal(z, [(2.0 * ((w[k] + 0.5) * q) - 1.0) * sw[k] for k in range(6)])
+
+
+def test_sampler_draws_are_uniform_and_independent(orc):
+    from scipy import stats
+    g, sw = _gate_and_widths(orc)
+    n = 6000
+    Z = np.array([S.draw(orc, sw, 5, c) for c in range(n)]).T
+    assert (np.abs(Z) < sw[:, None]).all()
+    U = (Z / sw[:, None] + 1.0) / 2.0
+    for k in range(6):
+        assert stats.kstest(U[k], "uniform").pvalue > 1e-3, k
+    C = np.corrcoef(U)
+    assert np.abs(C - np.eye(6)).max() < 0.06
+    # other seeds and candidates beyond 2^32 give other points
+    assert not np.array_equal(S.draw(orc, sw, 5, 7), S.draw(orc, sw, 6, 7))
+    assert not np.array_equal(S.draw(orc, sw, 5, 7), S.draw(orc, sw, 5, 7 + 2 ** 32))

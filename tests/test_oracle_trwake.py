@@ -74,6 +74,41 @@ def test_dipole_histogram_brute_force(orc):
     assert np.array_equal(np.bincount(bins[bins >= 0], minlength=nb), cnt)
 
 
+def test_dipole_sums_are_within_half_a_quantum_per_particle_of_the_plain_sum(orc):
+    """Each bin's fixed-point sum, read in metres, differs from the exact sum
+    of its particles' raw x (and y) by at most half a quantum (2^-41 m) per
+    particle, plus what the clamp to [-1, 1] m removes; non-finite
+    coordinates count 0.  The reference is exact rational arithmetic on the
+    raw coordinates (math.fsum gives the same to one rounding)."""
+    rng = np.random.default_rng(7)
+    n, nb = 20000, 128
+    s = rng.normal(0, 1e-3, n)
+    x = rng.normal(3e-4, 2e-3, n) * np.exp(rng.uniform(-8, 0, n))
+    y = rng.standard_t(3, n) * 1e-3
+    x[::211] = rng.uniform(1.0, 5.0, x[::211].size) * rng.choice([-1, 1], x[::211].size)
+    y[::307] = np.nan
+    lost = np.full(n, -1, np.int64)
+    lost[::7] = 2
+    rg, cnt, dx, dy = orc.dipole_histogram(s, x, y, lost, nb)
+    bins = brute_bins(s, lost < 0, nb)
+    for row, coord in ((dx, x), (dy, y)):
+        for b in range(nb):
+            sel = coord[bins == b]
+            fin = sel[np.isfinite(sel)]
+            exact = sum((Fraction(float(v)) for v in fin), Fraction(0))
+            clamp = sum((Fraction(abs(float(v))) - 1 for v in fin if abs(v) > 1.0), Fraction(0))
+            got = Fraction(int(row[b]), Q40)
+            err = abs(got - exact)
+            assert err <= Fraction(len(fin), 2 * Q40) + clamp, (b, float(err))
+            if clamp == 0 and len(fin):
+                assert abs(float(got) - math.fsum(fin)) <= len(fin) * 2.0 ** -41 + 1e-300
+    # the bins together hold the whole (clamped) sum
+    al = (lost < 0) & np.isfinite(x)
+    tot = Fraction(sum(int(v) for v in dx), Q40)
+    ref = sum((Fraction(float(v)) for v in np.clip(x[al], -1.0, 1.0)), Fraction(0))
+    assert abs(tot - ref) <= Fraction(int(al.sum()), 2 * Q40)
+
+
 def test_dipole_sums_are_modulo_2_64(orc):
     """2^23 particles at x = +1 m overflow the running sum, one at x = -1 m
     brings the total back into range: the modular sum is still exact."""
