@@ -154,7 +154,8 @@ typedef struct trk_opts {
                                    pass [eV/c]; raised by V cos(phase) per RFCA */
   double *moments;              /* NULL or device [passes][28]: per pass, after its
                                    last element: n, mean[6], central second
-                                   moments upper triangle row-major [21] */
+                                   moments upper triangle row-major [21]
+                                   (all 0 when nobody is alive) */
 } trk_opts;
 
 /* Device workspace needed by trk_track and the collective calls for a beam of
@@ -229,7 +230,8 @@ int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
 
 /* moments (Sec. 2.4 reductions): out_dev[28] = n, mean[6], central second
  * moments [21] (population normalisation) over alive particles, two passes,
- * fixed-order binary64 trees (deterministic for a given n_total). */
+ * fixed-order binary64 trees (deterministic for a given n_total); all 28
+ * entries 0 when nobody is alive. */
 int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t workspace_bytes,
                 void *stream);
 
@@ -290,8 +292,10 @@ typedef struct trk_batch_tuning {
 size_t trk_batch_workspace_size(const trk_batch *b, int32_t passes_per_launch);
 
 /* beam: the concatenated beam (n_total = seg_off[nvar]; n_alive unused);
- * moments_dev: NULL or [nvar][passes][28] (as trk_opts.moments, unshifted
- * one-pass sums). */
+ * moments_dev: NULL or [nvar][passes][28] (as trk_opts.moments: one-pass
+ * sums of the coordinates shifted by each variant's mean at the entry of the
+ * call, fixed-order reductions; all 28 entries 0 for a variant with nobody
+ * alive). */
 int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes, int32_t first_pass,
                       const trk_batch_tuning *tune, double *moments_dev, void *workspace,
                       size_t workspace_bytes, void *stream);

@@ -792,11 +792,17 @@ static double csum(const double *a, int64_t n) {
 
 /* Beam moments over alive particles (the centroid and second-moment
  * reductions of Sec. 2.4): n, the six means and the 21 central second
- * moments (population normalisation), two passes with compensated sums. */
+ * moments (population normalisation), two passes with compensated sums.
+ * With no particle alive every entry is 0 (the paper defines no moments of
+ * an empty beam; 0 stands in for the undefined 0/0). */
 void orc_moments(const orc_beam *b, double out[28]) {
   int64_t nal = 0;
   for (int64_t i = 0; i < b->n; ++i)
     if (b->lost_at[i] < 0) ++nal;
+  if (nal == 0) {
+    for (int k = 0; k < 28; ++k) out[k] = 0.0;
+    return;
+  }
   double *buf = (double *)malloc((size_t)(nal > 0 ? nal : 1) * sizeof(double));
   double mean[6];
   out[0] = (double)nal;

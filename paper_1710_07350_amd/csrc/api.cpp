@@ -1240,18 +1240,33 @@ extern "C" void trk_batch_destroy(trk_batch *b) {
   delete b;
 }
 
+// Batch workspace: the ticket counter (256 B), the moment rows
+// [chunks][ppl][28], the variants' moment shifts [nvar][6] and the per-chunk
+// sums of the mean at entry [chunks][7] (chunks counted at one particle per
+// thread, the most).
+namespace {
+size_t batch_mom_bytes(const trk_batch *b, int64_t ppl) {
+  return static_cast<size_t>(b->chunk_off[0][b->nvar]) * ppl * 28 * sizeof(double);
+}
+size_t batch_shift_bytes(const trk_batch *b) {
+  return (static_cast<size_t>(b->nvar) * 6 * sizeof(double) + 255) / 256 * 256;
+}
+}  // namespace
+
 extern "C" size_t trk_batch_workspace_size(const trk_batch *b, int32_t passes_per_launch) {
   if (b == nullptr) return 0;
   const int64_t ppl = std::max(1, std::min<int>(passes_per_launch <= 0 ? kBatchMomPasses : passes_per_launch,
                                                 kBatchMomPasses));
-  return 256 + static_cast<size_t>(b->chunk_off[0][b->nvar]) * ppl * 28 * sizeof(double) + 256;
+  return 256 + (batch_mom_bytes(b, ppl) + 255) / 256 * 256 + batch_shift_bytes(b) +
+         static_cast<size_t>(b->chunk_off[0][b->nvar]) * 7 * sizeof(double) + 256;
 }
 
 namespace {
 // enqueue the launches of one batched call on st
 hipError_t batch_sequence(trk_batch *b, const trk_beam *beam, int passes, int first_pass,
                           const trk_batch_tuning &tu, double *moments, uint32_t *ticket,
-                          double *mom_part, int ppl, hipStream_t st) {
+                          double *mom_part, double *shift, double *mean_part, int ppl,
+                          hipStream_t st) {
   const int k = ppt_slot(tu.ppt);
   const int grid = std::max(1, tu.blocks_per_cu) * std::max(1, b->ncu);
   BatchArgs a;
@@ -1273,6 +1288,12 @@ hipError_t batch_sequence(trk_batch *b, const trk_beam *beam, int passes, int fi
   a.ticket = ticket;
   a.total = b->chunk_off[k][b->nvar];
   a.mom_part = moments ? mom_part : nullptr;
+  a.mom_shift = shift;
+  a.mean_part = mean_part;
+  if (moments) {
+    hipError_t e = launch_batch_mean(a, ppt_of_slot(k), st);
+    if (e != hipSuccess) return e;
+  }
   for (int p0 = 0; p0 < passes; p0 += ppl) {
     const int np = std::min(ppl, passes - p0);
     a.pass0 = first_pass + p0;
@@ -1282,8 +1303,8 @@ hipError_t batch_sequence(trk_batch *b, const trk_beam *beam, int passes, int fi
     e = launch_batch(a, b->feat, ppt_of_slot(k), grid, st);
     if (e != hipSuccess) return e;
     if (moments) {
-      e = launch_batch_mom_finalize(mom_part, b->d_chunk_off[k], b->nvar, np, moments, p0, passes,
-                                    st);
+      e = launch_batch_mom_finalize(mom_part, b->d_chunk_off[k], shift, b->nvar, np, moments, p0,
+                                    passes, st);
       if (e != hipSuccess) return e;
     }
   }
@@ -1311,10 +1332,15 @@ extern "C" int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t pas
   if (int r = check_dev(workspace, "workspace")) return r;
   if (passes == 0 || beam->n_total == 0) return TRK_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t *ticket = static_cast<uint32_t *>(workspace);
-  double *mom_part = reinterpret_cast<double *>(static_cast<char *>(workspace) + 256);
+  char *wsb = static_cast<char *>(workspace);
+  uint32_t *ticket = reinterpret_cast<uint32_t *>(wsb);
+  double *mom_part = reinterpret_cast<double *>(wsb + 256);
+  const size_t mom_b = (batch_mom_bytes(b, ppl) + 255) / 256 * 256;
+  double *shift = reinterpret_cast<double *>(wsb + 256 + mom_b);
+  double *mean_part = reinterpret_cast<double *>(wsb + 256 + mom_b + batch_shift_bytes(b));
   if (!tune->use_graph) {
-    HIP_TRY(batch_sequence(b, beam, passes, first_pass, *tune, moments_dev, ticket, mom_part, ppl, st),
+    HIP_TRY(batch_sequence(b, beam, passes, first_pass, *tune, moments_dev, ticket, mom_part, shift,
+                           mean_part, ppl, st),
             "batch");
     return TRK_OK;
   }
@@ -1333,7 +1359,7 @@ extern "C" int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t pas
     if (b->cap == nullptr) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "stream");
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t e = batch_sequence(b, beam, passes, first_pass, *tune, moments_dev, ticket, mom_part,
-                                  ppl, b->cap);
+                                  shift, mean_part, ppl, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess) return hip_fail(e, "batch capture");

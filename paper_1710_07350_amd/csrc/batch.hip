@@ -10,8 +10,10 @@
 // A chunk runs all its passes in registers, exactly as the fused run kernel
 // does for one lattice, so every particle's trajectory equals that of its
 // variant tracked alone.  Per-chunk, per-pass moment rows are reduced per
-// variant in fixed order afterwards.  Particles stay in place; lost ones are
-// marked in lost_at.
+// variant in fixed order afterwards; they are sums of coordinates shifted by
+// the variant's mean at the entry of the call, so that an offset beam (a
+// closed-orbit offset, a large s) does not cancel in the central moments.
+// Particles stay in place; lost ones are marked in lost_at.
 #include <utility>
 
 #include "apply.h"
@@ -76,8 +78,15 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
 #pragma unroll
         for (int q = 0; q < kP; ++q) apply<kFeat>(E, pool, cx, p, gp, e, z[q], alive[q], rec[q], pid[q]);
       }
-      if (a.mom_part != nullptr)
-        block_moment_row_multi<kP>(alive, z, a.mom_part + (t * a.npass + p) * 28);
+      if (a.mom_part != nullptr) {
+        const double *sh = a.mom_shift + static_cast<int64_t>(v) * 6;
+        double d[kP][6];
+#pragma unroll
+        for (int q = 0; q < kP; ++q)
+#pragma unroll
+          for (int k = 0; k < 6; ++k) d[q][k] = alive[q] ? z[q][k] - sh[k] : 0.0;
+        block_moment_row_multi<kP>(alive, d, a.mom_part + (t * a.npass + p) * 28);
+      }
     }
 #pragma unroll
     for (int q = 0; q < kP; ++q) {
@@ -91,9 +100,64 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchArgs a) {
   }
 }
 
-// One block per (variant, pass): rows of the variant's chunks in order.
+// Mean at entry of each variant (the shift of its moment rows): one block
+// per chunk of kBlock*kP slots sums (n, z_k) over its alive particles, then
+// one block per variant adds its chunks' rows in order; 0 when none is alive.
+template <int kP>
+__global__ __launch_bounds__(kBlock) void k_batch_mean_partial(const BatchArgs a) {
+  const int64_t t = blockIdx.x;
+  int lo = 0, hi = a.nvar;  // chunk_off[lo] <= t < chunk_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.chunk_off[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int v = lo;
+  const int64_t s1 = a.seg_off[v + 1];
+  const int64_t base =
+      a.seg_off[v] + (t - a.chunk_off[v]) * (static_cast<int64_t>(kBlock) * kP) + threadIdx.x;
+  double acc[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kP; ++q) {
+    const int64_t i = base + q * kBlock;
+    if (i < s1 && a.lost_at[i] < 0) {
+      acc[0] += 1.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[1 + k] += a.z[k][i];
+    }
+  }
+  const double *tot = block_sum<7>(acc);
+  if (threadIdx.x < 7) a.mean_part[t * 7 + threadIdx.x] = tot[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_mean_finalize(const double *__restrict__ part,
+                                                                const int64_t *__restrict__ chunk_off,
+                                                                double *__restrict__ shift) {
+  const int v = blockIdx.x;
+  double acc[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) acc[k] = 0.0;
+  for (int64_t c = chunk_off[v] + threadIdx.x; c < chunk_off[v + 1]; c += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) acc[k] += part[c * 7 + k];
+  }
+  const double *tot = block_sum<7>(acc);
+  if (threadIdx.x < 6) {
+    const double n = tot[0];
+    shift[static_cast<int64_t>(v) * 6 + threadIdx.x] = n > 0.0 ? tot[1 + threadIdx.x] / n : 0.0;
+  }
+}
+
+// One block per (variant, pass): rows of the variant's chunks in order, then
+// mean_k = shift_k + S_k/n, cov_kl = S_kl/n - (S_k/n)(S_l/n) on the shifted
+// sums; every output 0 for a variant with nobody alive.
 __global__ __launch_bounds__(kBlock) void k_batch_mom_finalize(const double *__restrict__ part,
                                                                const int64_t *__restrict__ chunk_off,
+                                                               const double *__restrict__ shift,
                                                                int npass, double *__restrict__ out,
                                                                int out_pass0, int out_passes) {
   const int v = blockIdx.x / npass, p = blockIdx.x % npass;
@@ -109,10 +173,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_mom_finalize(const double *__r
   if (threadIdx.x == 0) {
     double *o = out + (static_cast<int64_t>(v) * out_passes + out_pass0 + p) * 28;
     const double n = tot[0];
+    if (n == 0.0) {
+      for (int k = 0; k < 28; ++k) o[k] = 0.0;
+      return;
+    }
+    const double *sh = shift + static_cast<int64_t>(v) * 6;
     double m[6];
     for (int k = 0; k < 6; ++k) m[k] = tot[1 + k] / n;
     o[0] = n;
-    for (int k = 0; k < 6; ++k) o[1 + k] = m[k];
+    for (int k = 0; k < 6; ++k) o[1 + k] = sh[k] + m[k];
     int idx = 7;
     for (int k = 0; k < 6; ++k)
       for (int l = k; l < 6; ++l, ++idx) o[idx] = tot[idx] / n - m[k] * m[l];
@@ -146,11 +215,26 @@ hipError_t launch_batch(const BatchArgs &a, uint32_t feat, int ppt, int grid, hi
   return hipGetLastError();
 }
 
-hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_off, int nvar,
-                                     int npass, double *out, int out_pass0, int out_passes,
-                                     hipStream_t st) {
+hipError_t launch_batch_mean(const BatchArgs &a, int ppt, hipStream_t st) {
+  const int64_t total = a.total;
+  if (ppt >= 4)
+    hipLaunchKernelGGL((k_batch_mean_partial<4>), dim3(total), dim3(kBlock), 0, st, a);
+  else if (ppt == 2)
+    hipLaunchKernelGGL((k_batch_mean_partial<2>), dim3(total), dim3(kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_batch_mean_partial<1>), dim3(total), dim3(kBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_mean_finalize, dim3(a.nvar), dim3(kBlock), 0, st, a.mean_part,
+                     a.chunk_off, const_cast<double *>(a.mom_shift));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_off,
+                                     const double *shift, int nvar, int npass, double *out,
+                                     int out_pass0, int out_passes, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_mom_finalize, dim3(nvar * npass), dim3(kBlock), 0, st, part,
-                     chunk_off, npass, out, out_pass0, out_passes);
+                     chunk_off, shift, npass, out, out_pass0, out_passes);
   return hipGetLastError();
 }
 

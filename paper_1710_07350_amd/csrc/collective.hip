@@ -471,7 +471,8 @@ hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_
 }
 
 // One block per pass: sum the rows in fixed order, then
-// mean_k = shift_k + S_k/n, cov_kl = S_kl/n - (S_k/n)(S_l/n).
+// mean_k = shift_k + S_k/n, cov_kl = S_kl/n - (S_k/n)(S_l/n); with nobody
+// alive every output (and the mean handed on as the next shift) is 0.
 __global__ __launch_bounds__(kBlock) void k_mom_finalize(const double *__restrict__ part, int nrows,
                                                          const double *__restrict__ shift,
                                                          double *__restrict__ out, int out_stride,
@@ -488,6 +489,12 @@ __global__ __launch_bounds__(kBlock) void k_mom_finalize(const double *__restric
   if (threadIdx.x == 0) {
     double *o = out + static_cast<int64_t>(blockIdx.x) * out_stride;
     const double n = tot[0];
+    if (n == 0.0) {
+      for (int k = 0; k < 28; ++k) o[k] = 0.0;
+      if (mean_out)
+        for (int k = 0; k < 6; ++k) mean_out[k] = 0.0;
+      return;
+    }
     double m[6];
     for (int k = 0; k < 6; ++k) m[k] = tot[1 + k] / n;
     o[0] = n;

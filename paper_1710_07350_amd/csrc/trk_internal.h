@@ -12,7 +12,7 @@ namespace trk {
 constexpr int kBlock = 256;
 // copies of the counts a run-binned histogram merges into (spreads the
 // same-address contention of up to kMaxRunGrid workgroups)
-constexpr int kHistCopies = 8;        // threads per block of the particle kernels
+constexpr int kHistCopies = 8;
 constexpr int kMaxVar = 96;        // pass-varying constants per fused launch
 constexpr int kMaxGridStride = 2048;
 constexpr int kMaxPassesPerLaunch = 64;
@@ -126,11 +126,15 @@ struct BatchArgs {
   uint32_t *ticket;          // zeroed before the launch
   int64_t total;             // tickets
   double *mom_part;          // [total][npass][28] or null
+  const double *mom_shift;   // [nvar][6] moment shift: each variant's mean at entry
+  double *mean_part;         // [total][7] (n, sum z_k) per chunk, for the shift
 };
 hipError_t launch_batch(const BatchArgs &a, uint32_t feat, int ppt, int grid, hipStream_t st);
-hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_off, int nvar,
-                                     int npass, double *out, int out_pass0, int out_passes,
-                                     hipStream_t st);
+// the variants' means at entry into a.mom_shift (a.mean_part as scratch)
+hipError_t launch_batch_mean(const BatchArgs &a, int ppt, hipStream_t st);
+hipError_t launch_batch_mom_finalize(const double *part, const int64_t *chunk_off,
+                                     const double *shift, int nvar, int npass, double *out,
+                                     int out_pass0, int out_passes, hipStream_t st);
 
 // ---------------------------------------------------------------- workspace
 struct Workspace {

@@ -122,6 +122,18 @@ def test_wake_kick_linear_in_charge(orc):
 
 
 # ------------------------------------------------------------------ moments
+def test_moments_of_an_empty_beam_are_zero(orc):
+    """Nobody alive: n = 0 and every mean and second moment 0 (the reading
+    for the undefined 0/0); one survivor: its coordinates and zero spread."""
+    z = np.random.default_rng(6).normal(0, 1e-3, (6, 40))
+    b = orc.Beam(z, np.arange(40, dtype=np.uint32), np.full(40, 3, np.int64))
+    assert (orc.moments(b) == 0).all()
+    lost = np.full(40, 3, np.int64)
+    lost[17] = -1
+    m = orc.moments(orc.Beam(z, np.arange(40, dtype=np.uint32), lost))
+    assert m[0] == 1 and np.array_equal(m[1:7], z[:, 17]) and (m[7:] == 0).all()
+
+
 def test_moments_vs_fsum(orc):
     rng = np.random.default_rng(5)
     z = rng.normal(0, [[1e-3], [1e-4], [1e-3], [1e-4], [1e-3], [1e-3]], (6, 3000))
