@@ -1,29 +1,38 @@
 #!/usr/bin/env python3
 """Throughput benchmark: particle-element steps per second on one MI355X.
 
-Default workload: the linac bunch compressor -- 4e6 particles of a chirped 6D
-Gaussian beam through 8 zero-length RF cavities, each followed by the
-longitudinal wake step (1024-bin histogram of s, FP32 matrix-core causal
-convolution with a resonator wake, interpolated energy kick), then a
-second-order chicane map (17 elements per pass).  One step = one pass of a
-fresh, already device-resident batch.  A particle-element step is one element
-applied to one particle alive at its entry.
+Headline workload (the JSON line's `value`): the linac bunch compressor --
+4e6 particles of a chirped 6D Gaussian beam through 8 zero-length RF
+cavities, each followed by the longitudinal wake step (1024-bin histogram of
+s, FP32 matrix-core causal convolution with a resonator wake, interpolated
+energy kick), then a second-order chicane map (17 elements per pass).  One
+step = one pass of a fresh, already device-resident batch.  A
+particle-element step is one element applied to one particle alive at its
+entry.
 
-Prints one JSON line with the throughput, the roofline position of the
-dominant kernel (the fused element-run kernel, timed with HIP events on its
-stream during the timed steps) and the CPU oracle timed on a bounded sample.
+The default run adds, under "configs", every other configured workload with
+its own roofline and CPU-oracle baseline: the FODO channel (1e4 particles,
+100 passes), the FODO channel at 1e7 particles one element per launch (HBM
+bound) and whole passes fused (FP64 bound), the storage ring as one
+1000-turn call (1e6 particles, moments every turn), the batched scan (256
+ring variants, 200 turns, against the variants tracked one at a time), the
+bunch compressor at 4e7 particles (beyond the 256 MB Infinity Cache), the
+sweep of the particle count from 1e4 to 1e7, the fused-against-separate
+moment reductions and the learned section surrogate.
 
-  python bench.py [--steps K] [--warmup W] [--workload bc|ring|fodo|roof|surr]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--headline-only]
 
-The surr workload measures the learned section surrogate instead: it trains
-the network on the GPU (pairs from the tracker over the admitted part of the
-+-6 sigma box), then times one pass through the first ten ring cells with
-plain tracking and with gate + network + fallback on 1e7 fresh particles,
-and reports the speed-up and the surrogate's error against the tracker.
+Rooflines: the dominant kernel's duration comes from start and stop events
+that its own dispatch packet records (hipExtLaunchKernel), accumulated over
+a timed region on the kernel's stream; the algorithmic bytes or flops per
+launch are stated per workload.  `--workload ceilings` measures the box's
+copy, read and FP64 FMA ceilings; `--workload copycal` is a plain copy of
+known size for calibrating the HBM byte counters.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -46,6 +55,10 @@ TRAFFIC_PER_LAUNCH = {("bc", 0): 101947278, ("roof", 1): 734090445}
 # run in which nobody is lost (profiles/k_run_fp64_flops.md)
 FP64_PEAK_TFLOPS = 78.6
 FP64_FLOP_PER_STEP = {"ring": 135.8, "fodo": 60.0, "fodo3": 72.7}
+BF16_PEAK_TFLOPS = 2500.0
+STEP_UNIT = "particle·element steps/s"
+KINDS = ("bc", "rfcw", "ring", "fodo", "roof", "surr", "batch", "compact", "sweep",
+         "ablation", "ceilings", "copycal")
 
 
 def parse():
@@ -53,21 +66,30 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="bc",
-                    choices=["bc", "rfcw", "ring", "fodo", "roof", "surr", "batch", "compact"])
+    ap.add_argument("--workload", default="bc", choices=KINDS)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: skip the nested configurations")
     ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
     ap.add_argument("--precision", default="bf16x2", choices=["bf16", "bf16x2"])
+    ap.add_argument("--margin", type=float, default=0.5, help="surrogate gate margin")
     ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
     ap.add_argument("--quad-order", type=int, default=2, choices=[2, 3],
                     help="fodo/roof: track the quadrupoles with second- or third-order maps")
+    ap.add_argument("--turns", type=int, default=None, help="ring: turns per call; batch: turns")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--particles", type=float, default=None)
     ap.add_argument("--sigma-scale", type=float, default=1.0,
                     help="scale the Gaussian beam's sigmas (0.1: nobody is lost)")
+    ap.add_argument("--mib", type=int, default=1024, help="copycal: MiB copied")
     return ap.parse_args()
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ counting
 def run_mask_bytes(lattice, e0, e1, moments=False, next_wake=False):
     """Algorithmic bytes per particle of one fused launch over elements
     [e0, e1): each coordinate read by the run is loaded once and each one it
@@ -132,18 +154,6 @@ def launches_of(lattice, passes_per_launch=16, max_e=0):
     return out
 
 
-def cpu_baseline(lattice, beam_kw, passes, p_ref, sample_n, seed=0):
-    import oracle
-    from paper_1710_07350_amd import inputs
-    d = inputs.gaussian_beam(sample_n, **{k: v for k, v in beam_kw.items() if k != "n"})
-    b = oracle.Beam.from_inputs(d)
-    t0 = time.perf_counter()
-    oracle.track(b, lattice, passes, p_ref=p_ref, seed=seed)
-    dt = time.perf_counter() - t0
-    steps = element_steps(lattice, passes, sample_n, b.lost_at, 0)
-    return steps / dt, dt, oracle.get_threads()
-
-
 def element_steps(lattice, passes, n, lost_at, first_pass):
     """Exact particle-element steps: survivors traverse every element of every
     pass; a particle lost at (pass, element) traversed up to that element."""
@@ -156,23 +166,263 @@ def element_steps(lattice, passes, n, lost_at, first_pass):
     return float(alive) * passes * nel + float((p * nel + e + 1).sum())
 
 
-def surrogate_bench(args):
-    """Train the section surrogate, then time plain tracking against
-    gate + network + fallback on fresh particles of two distributions."""
+# ------------------------------------------------------------------ CPU oracle
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(lattice, beam_kw, passes, p_ref, n_all, n_one=None, seed=0, what=""):
+    """The CPU oracle on the workload's own lattice and beam (the first
+    n_all particles of it; particles are independent and their random kicks
+    keyed by id), timed on all host threads and on one thread (the first
+    n_one particles).  Returns the cpu_baseline object."""
+    import oracle
+    from paper_1710_07350_amd import inputs
+    kw = {k: v for k, v in beam_kw.items() if k != "n"}
+    threads = oracle.get_threads()
+
+    def one(n):
+        d = inputs.gaussian_beam(n, **kw)
+        b = oracle.Beam.from_inputs(d, n0=beam_kw.get("n"))
+        t0 = time.perf_counter()
+        oracle.track(b, lattice, passes, p_ref=p_ref, seed=seed)
+        dt = time.perf_counter() - t0
+        return element_steps(lattice, passes, n, b.lost_at, 0) / dt, dt
+
+    v_all, t_all = one(n_all)
+    n_one = n_one or n_all
+    oracle.set_threads(1)
+    try:
+        v_one, t_one = one(n_one)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": v_all, "unit": STEP_UNIT, "cores": threads, "kind": "oracle",
+            "value_1core": v_one, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{what}: {n_all} particles on {threads} threads ({t_all:.1f} s), "
+                      f"{n_one} on 1 thread ({t_one:.1f} s), {passes} passes each"}
+
+
+# ------------------------------------------------------------------ tracking workloads
+def track_workload(wl, args, n=None, steps=None, warm=None, fusion=None, passes=None,
+                   cpu=True, roof=True):
+    """Time `steps` tracking steps of workload wl (bc, rfcw, fodo, roof, ring)
+    after `warm` untimed ones; returns the result object (without the
+    contract's outer fields when nested)."""
     import torch
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs
 
-    torch.cuda.set_device(0)
-    n = int(args.particles or 10_000_000)
+    fusion = args.fusion if fusion is None else fusion
+    wake_mode = B.WAKE_FP32_MFMA if args.wake_mode == "fp32" else B.WAKE_FP64
+    sig = None
+    if args.sigma_scale != 1.0:
+        sig = tuple(args.sigma_scale * v for v in inputs.BEAM_SIGMAS)
+    use_mom = False
+    if wl in ("bc", "rfcw"):
+        lat = inputs.bc_lattice() if wl == "bc" else inputs.rfcw_lattice()
+        n = int(n or args.particles or 4_000_000)
+        beam_kw = dict(n=n, seed=0, chirp=inputs.BC_CHIRP)
+        p_ref, pps = inputs.BC_P0_EV, 1
+        steps = steps or args.steps or 50
+        warm = warm if warm is not None else (args.warmup if args.warmup is not None else 5)
+        cfg = {"workload": (f"linac bunch compressor: {n:.0e}-particle chirped Gaussian beam, "
+                            "8 x (RF cavity + 1024-bin wake step) + 2nd-order chicane")
+               if wl == "bc" else
+               (f"linac bunch compressor with transverse wakes: {n:.0e}-particle chirped "
+                "Gaussian beam, 8 x (RF cavity + 1024-bin longitudinal and transverse wake "
+                "steps) + 2nd-order chicane"),
+               "particles": n, "elements_per_pass": len(lat),
+               "wake_convolution": "fp32-mfma" if wake_mode == B.WAKE_FP32_MFMA else "fp64",
+               "batch": "fresh device-resident beam per step"}
+        cpu_n = (n, n) if n <= 4_000_000 else (4_000_000, 1_000_000)
+    elif wl == "ring":
+        lat = inputs.ring_lattice(seed=0)
+        n = int(n or args.particles or 1_000_000)
+        beam_kw = dict(n=n, seed=0)
+        if sig:
+            beam_kw["sigmas"] = sig
+        p_ref = 1e9
+        pps = int(passes or args.turns or 1000)
+        steps = steps or args.steps or 2
+        warm = warm if warm is not None else (args.warmup if args.warmup is not None else 1)
+        use_mom = True
+        cfg = {"workload": f"storage ring: {n:.0e} particles, {pps} turns in one call, 40 cells of "
+                           "Yoshida-4 kick-drift quads and sector bends, random thin sextupoles, "
+                           "Philox radiation kick, elliptical aperture with compaction, moments "
+                           "every turn",
+               "particles": n, "elements_per_pass": len(lat), "turns_per_call": pps,
+               "batch": "fresh device-resident beam per call"}
+        cpu_n = (2000, 500)
+    else:  # fodo / roof
+        lat = inputs.fodo_lattice(quad_order=args.quad_order)
+        n = int(n or args.particles or (10_000 if wl == "fodo" else 10_000_000))
+        beam_kw = dict(n=n, seed=0)
+        if sig:
+            beam_kw["sigmas"] = sig
+        p_ref = 1e9
+        pps = int(passes or (10 if wl == "roof" else 100))
+        steps = steps or args.steps or 5
+        warm = warm if warm is not None else (args.warmup if args.warmup is not None else 1)
+        cfg = {"workload": f"FODO channel: {n:.0e} particles, 10 cells (60 elements) per pass, "
+                           f"{pps} passes per step"
+                           + (f", at most {fusion} elements per launch" if fusion else
+                              ", whole passes fused")
+                           + (", third-order quadrupole maps" if args.quad_order == 3 else ""),
+               "particles": n, "elements_per_pass": len(lat), "fusion_max_elements": fusion,
+               "quad_order": args.quad_order, "batch": "fresh device-resident beam per step"}
+        cpu_n = (n, n) if n <= 10_000 else (100_000, 20_000)
+
+    L = B.Lattice(lat)
+    d = inputs.gaussian_beam(**beam_kw)
+    template = B.Beam.from_inputs(d)
+    del d
+    ws = B.Workspace(n)
+    nb = warm + 2 * steps
+    beams = []
+    for _ in range(nb):
+        b = B.Beam.__new__(B.Beam)
+        b.n = n
+        b.z = template.z.clone()
+        b.id = template.id.clone()
+        b.lost_at = template.lost_at.clone()
+        b.n_alive = template.n_alive.clone()
+        beams.append(b)
+    del template
+    mom = torch.zeros((max(pps, 1), 28), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def one_step(i):
+        B.track(beams[i], L, pps, ws, seed=7, first_pass=0, p_ref=p_ref,
+                moments=mom if use_mom else None, wake_mode=wake_mode,
+                max_elems_per_launch=fusion, stream=stream)
+
+    def timed(i0, i1):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for i in range(i0, i1):
+            one_step(i)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    for i in range(warm):
+        one_step(i)
+    torch.cuda.synchronize()
+    # two timed regions of `steps` steps each: the first gives the
+    # throughput, the second the run kernel's launch durations (start and
+    # stop events recorded by each run's own dispatch, class 0)
+    ms_total = timed(warm, warm + steps)
+    B.profile_enable(True, classes=0b1101)
+    timed(warm + steps, warm + 2 * steps)
+    run_ms, run_launches = B.profile_read(0)
+    hist_ms, hist_n = B.profile_read(2)
+    conv_ms, conv_n = B.profile_read(3)
+    B.profile_enable(False)
+
+    def steps_of(i0, i1):
+        tot = 0.0
+        for i in range(i0, i1):
+            tot += element_steps(lat, pps, n, beams[i].lost_at.cpu().numpy(), 0)
+        return tot
+
+    total_steps = steps_of(warm, warm + steps)
+    value = total_steps / (ms_total / 1e3)
+    prof_steps = steps_of(warm + steps, warm + 2 * steps)
+    alive_end = int(beams[warm].n_alive.item())
+    out = {"metric": "particle·element steps/s (FP64 tracking)", "value": value,
+           "unit": STEP_UNIT, "steps": steps, "warmup": warm, "ms_per_step": ms_total / steps,
+           "dtype": "f64", "config": cfg, "alive_after_step": alive_end}
+    kernels = {"run": {"launches": run_launches, "avg_us": 1e3 * run_ms / max(run_launches, 1)}}
+    if hist_n:
+        kernels["histogram"] = {"launches": hist_n, "avg_us": 1e3 * hist_ms / hist_n}
+    if conv_n:
+        kernels["convolution"] = {"launches": conv_n, "avg_us": 1e3 * conv_ms / conv_n}
+    out["kernel_time"] = kernels
+
+    if roof:
+        plan = launches_of(lat, 16, fusion)
+        bytes_per_pass = 0.0
+        launches_per_pass = 0.0
+        for j, (e0, e1, npass) in enumerate(plan):
+            nxt = plan[(j + 1) % len(plan)][0] if len(plan) > 1 else None
+            next_wake = nxt is not None and lat[nxt].kind in WAKES and (j + 1 < len(plan))
+            per = run_mask_bytes(lat, e0, e1, moments=(use_mom and e1 == len(lat)),
+                                 next_wake=next_wake)
+            if npass > 1:
+                bytes_per_pass += per / npass
+                launches_per_pass += 1.0 / npass
+            else:
+                bytes_per_pass += per
+                launches_per_pass += 1.0
+        alive_mean = prof_steps / (steps * pps * len(lat))
+        alg_bytes_per_launch = alive_mean * bytes_per_pass / launches_per_pass
+        avg_ms = run_ms / max(run_launches, 1)
+        achieved = alg_bytes_per_launch / (avg_ms / 1e3) / 1e9
+        rf = {"bound": "hbm", "kernel": "trk::k_run (fused element run)",
+              "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved / HBM_PEAK_GBS, 4),
+              "traffic": (TRAFFIC_PER_LAUNCH.get((wl, fusion)) if args.quad_order == 2
+                          and n == (4_000_000 if wl == "bc" else 10_000_000) else None),
+              "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
+              "alg_bytes_per_launch": round(alg_bytes_per_launch),
+              "timing": "start/stop events recorded by each launch's dispatch packet"}
+        fkey = wl
+        if wl in ("fodo", "roof"):
+            fkey = "fodo3" if args.quad_order == 3 else "fodo"
+        fpp = FP64_FLOP_PER_STEP.get(fkey)
+        if fpp is not None:
+            steps_per_launch = prof_steps / max(run_launches, 1)
+            flops = fpp * steps_per_launch
+            # FP64 work per byte above the machine balance: bound by the
+            # FP64 vector units
+            if flops / max(alg_bytes_per_launch, 1.0) > FP64_PEAK_TFLOPS / (HBM_PEAK_GBS / 1e3):
+                ach = flops / (avg_ms / 1e3) / 1e12
+                rf.update({"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
+                           "traffic": None, "alg_flops_per_launch": flops,
+                           "fp64_flops_per_element_step": fpp})
+        out["roofline"] = rf
+    del beams
+    torch.cuda.empty_cache()
+    if cpu and not args.no_cpu_baseline:
+        log(f"{wl}: CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline(lat, beam_kw, pps, p_ref, cpu_n[0], cpu_n[1],
+                                           seed=7, what=f"{wl} workload")
+    return out
+
+
+# ------------------------------------------------------------------ surrogate
+def surrogate_bench(args, n=None):
+    """Train the section surrogate, then time plain tracking against
+    gate + network + fallback on fresh particles of three distributions."""
+    import torch
+    from paper_1710_07350_amd import binding as B
+    from paper_1710_07350_amd import inputs
+
+    n = int(n or args.particles or 10_000_000)
     prec = B.MLP_BF16X2 if args.precision == "bf16x2" else B.MLP_BF16
-    margin, aper = 0.5, (10e-3, 5e-3)
+    margin, aper = args.margin, (10e-3, 5e-3)
     hw = 6.0 * np.array(inputs.BEAM_SIGMAS)
     sec = inputs.ring_lattice(seed=0)[:100]
     L = B.Lattice(sec)
     sur = B.Surrogate(L, hw, margin, aper)
     ws = sur.workspace(n)
-    # training pairs: n admitted inputs from the sampler, tracked through the section
     t0 = time.perf_counter()
     beam = B.Beam.empty(n)
     B.surrogate_sample(sur, 5, 0, beam, ws)
@@ -181,7 +431,7 @@ def surrogate_bench(args):
     D = B.surrogate_fit_scale(sur, r, npairs, ws)
     del beam
     t_pairs = time.perf_counter() - t0
-    print(f"pairs: {npairs} in {t_pairs:.2f} s; D = {D}", file=sys.stderr, flush=True)
+    log(f"surrogate pairs: {npairs} in {t_pairs:.2f} s; D = {D}")
     inv = [1.0 / v if v > 0 else 0.0 for v in D]
     m = B.Mlp(inputs.mlp_init_params(21))
     batch = 8192
@@ -191,8 +441,8 @@ def surrogate_bench(args):
     loss = B.mlp_train(m, u, r, inv, mws, batch=batch, epochs=args.epochs, lr0=2e-3,
                        lr_min=1e-5, seed=9, precision=prec, n_pairs=npairs).cpu().numpy()
     t_train = time.perf_counter() - t0
-    print(f"training: {args.epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3e} -> "
-          f"{loss[-1]:.3e}", file=sys.stderr, flush=True)
+    log(f"surrogate training: {args.epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3e} -> "
+        f"{loss[-1]:.3e}")
     del u, r
 
     def one_set(d, name, reps=5):
@@ -223,8 +473,6 @@ def surrogate_bench(args):
                         got = work.host()
         infer_ms, infer_n = B.profile_read(1)
         B.profile_enable(False)
-        # surrogate error on admitted particles against the tracker, by id
-        nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
         work.copy_(src)
         adm = B.surrogate_gate(sur, work).cpu().numpy().astype(bool)
         ids = d["id"][adm]
@@ -250,7 +498,7 @@ def surrogate_bench(args):
                "rms_error": {k: float(np.sqrt((err[i] ** 2).mean())) if err.size else 0.0
                              for i, k in enumerate(names)},
                "infer_ms": infer_ms / max(infer_n, 1)}
-        print(json.dumps(out), file=sys.stderr, flush=True)
+        log(json.dumps(out))
         return out
 
     fresh = B.Beam.empty(n)
@@ -258,75 +506,31 @@ def surrogate_bench(args):
     fh = fresh.host()
     del fresh
     dom = one_set({"z": fh["z"], "id": fh["id"], "lost_at": fh["lost_at"]},
-                  "fresh uniform points of the training domain (box ∩ gate)")
+                  "fresh uniform points of the training domain (box and gate)")
     box = one_set(inputs.uniform_box_beam(n, seed=61, half_widths=hw), "uniform +-6 sigma box")
     gauss = one_set(inputs.gaussian_beam(n, seed=62), "Gaussian ring beam")
-    # 100 ring turns of 1e6 particles: the section served by the surrogate for
-    # admitted particles each turn (the rest of the ring tracked plainly),
-    # against the whole ring tracked plainly; Philox kicks are keyed by
-    # (id, turn), so both runs see the same kicks.
-    nr, turns = 1_000_000, 100
-    ring = inputs.ring_lattice(seed=0)
-    Lring, Lrest = B.Lattice(ring), B.Lattice(ring[100:])
-    d0 = inputs.gaussian_beam(nr, seed=64)
-    plain, served = B.Beam.from_inputs(d0), B.Beam.from_inputs(d0)
-    wsr = B.Workspace(nr)
-    wss = sur.workspace(nr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(turns):
-        B.track(plain, Lring, 1, wsr, seed=7, first_pass=t)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    nadm = torch.zeros(1, dtype=torch.int64, device="cuda")
-    adm_sum = 0
-    t0 = time.perf_counter()
-    for t in range(turns):
-        B.surrogate_apply(sur, m, served, wss, first_pass=t, precision=prec, n_admitted=nadm)
-        B.track(served, Lrest, 1, wsr, seed=7, first_pass=t)
-        adm_sum += nadm
-    torch.cuda.synchronize()
-    t_served = time.perf_counter() - t0
-    hp, hs = plain.host(), served.host()
-    both = np.intersect1d(hp["id"][:hp["n_alive"]], hs["id"][:hs["n_alive"]])
-    pp = np.empty(nr, np.int64)
-    pp[hp["id"]] = np.arange(nr)
-    ps = np.empty(nr, np.int64)
-    ps[hs["id"]] = np.arange(nr)
-    drift = np.abs(hs["z"][:, ps[both]] - hp["z"][:, pp[both]])
-    ring100 = {"particles": nr, "turns": turns, "alive_plain": hp["n_alive"],
-               "alive_served": hs["n_alive"],
-               "admitted_per_turn": float(adm_sum.item()) / turns / nr,
-               "s_plain": round(t_plain, 3), "s_served": round(t_served, 3),
-               "max_drift": {k: float(drift[i].max()) for i, k in
-                             enumerate(["x", "xp", "y", "yp", "s", "dp"])},
-               "rms_drift": {k: float(np.sqrt((drift[i] ** 2).mean())) for i, k in
-                             enumerate(["x", "xp", "y", "yp", "s", "dp"])}}
-    print(json.dumps(ring100), file=sys.stderr, flush=True)
     flops = 2.0 * (6 * 256 + 2 * 256 * 256 + 256 * 6)
     ach = dom["admitted"] * flops / (dom["infer_ms"] / 1e3) / 1e12
     mx = dom["max_abs_error"]
-    out = {"metric": "surrogate speedup over plain tracking of the section",
-           "value": dom["speedup"], "unit": "x", "n_gpus": 1, "steps": 5, "warmup": 1,
-           "ms_per_step": dom["ms_surrogate"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "bf16 network (" + args.precision + " activations), "
-                                              "f64 linear part and fallback",
-           "data": "synthetic",
-           "config": {"workload": "learned surrogate of ring cells 0-9 (100 elements), "
-                                  f"1e7 fresh particles, gate margin {margin}",
-                      "training_pairs": npairs, "epochs": args.epochs, "batch": batch,
-                      "train_s": round(t_train, 2), "final_loss": float(loss[-1])},
-           "error": {"max_m": max(mx["x"], mx["y"], mx["s"]), "max_rad": max(mx["xp"], mx["yp"]),
-                     "meets_1e-6": max(mx.values()) <= 1e-6},
-           "sets": [dom, box, gauss],
-           "ring_100_turns": ring100,
-           "roofline": {"bound": "mfma", "kernel": "trk::k_surr_infer", "achieved": round(ach, 2),
-                        "peak": 2500.0, "unit": "TFLOP/s", "frac": round(ach / 2500.0, 4),
-                        "traffic": None}}
-    print(json.dumps(out))
+    return {"metric": "surrogate speedup over plain tracking of the section",
+            "value": dom["speedup"], "unit": "x", "steps": 5, "warmup": 1,
+            "ms_per_step": dom["ms_surrogate"], "higher_is_better": True,
+            "dtype": "bf16 network (" + args.precision + " activations), f64 linear part and "
+                     "fallback",
+            "config": {"workload": "learned surrogate of ring cells 0-9 (100 elements), "
+                                   f"{n:.0e} fresh particles, gate margin {margin}",
+                       "training_pairs": npairs, "epochs": args.epochs, "batch": batch,
+                       "train_s": round(t_train, 2), "final_loss": float(loss[-1])},
+            "error": {"max_m": max(mx["x"], mx["y"], mx["s"]), "max_rad": max(mx["xp"], mx["yp"]),
+                      "meets_1e-6": max(mx.values()) <= 1e-6},
+            "sets": [dom, box, gauss],
+            "roofline": {"bound": "mfma", "kernel": "trk::k_surr_infer",
+                         "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None}}
 
 
-def batch_bench(args):
+# ------------------------------------------------------------------ batches
+def batch_bench(args, turns=None):
     """256 ring variants (own sextupoles, own seeds, log-uniform sizes in
     [1e3, 1e5]) in one persistent launch sequence (autotuned, hipGraph),
     against the same variants tracked one at a time with trk_track."""
@@ -335,9 +539,8 @@ def batch_bench(args):
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs
 
-    torch.cuda.set_device(0)
     nvar = 256
-    turns = args.steps or 20
+    turns = int(turns or args.turns or 200)
     sizes = inputs.batch_variant_sizes(nvar, seed=0)
     lats = [inputs.ring_lattice(seed=100 + v) for v in range(nvar)]
     beams = [inputs.gaussian_beam(int(n), seed=1000 + v) for v, n in enumerate(sizes)]
@@ -353,7 +556,7 @@ def batch_bench(args):
     t0 = time.perf_counter()
     tune = autotune.tune_batch(bt, work, probe_passes=4)
     t_tune = time.perf_counter() - t0
-    print(f"autotune: {tune} in {t_tune:.1f} s", file=sys.stderr, flush=True)
+    log(f"batch autotune: {tune} in {t_tune:.1f} s")
     tune = {k: tune[k] for k in ("ppt", "blocks_per_cu", "passes_per_launch")}
     ws = bt.workspace(64)
     mom = torch.zeros((nvar, turns, 28), dtype=torch.float64, device="cuda")
@@ -370,30 +573,22 @@ def batch_bench(args):
         return a.elapsed_time(b)
 
     batched()                                   # capture the graph
-    tb = float(np.median([batched() for _ in range(3)]))
+    tb = float(np.median([batched() for _ in range(2)]))
     res_b = work.host()
-    # one at a time
+    # one at a time (timed once: the kernels are warm from a two-turn call)
     vb = [B.Beam.from_inputs(b) for b in beams]
     vws = [B.Workspace(int(n)) for n in sizes]
     vmom = [torch.zeros((turns, 28), dtype=torch.float64, device="cuda") for _ in range(nvar)]
-    init = [(b.z.clone(), b.id.clone(), b.lost_at.clone(), b.n_alive.clone()) for b in vb]
-
-    def sequential():
-        for b, (z, i, l, na) in zip(vb, init):
-            b.z.copy_(z); b.id.copy_(i); b.lost_at.copy_(l); b.n_alive.copy_(na)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for v in range(nvar):
-            B.track(vb[v], Ls[v], turns, vws[v], seed=int(seeds[v]), moments=vmom[v])
-        e.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(e)
-
-    sequential()
-    ts = float(np.median([sequential() for _ in range(3)]))
-    # variant by variant: identical particles (by id) and loss records
+    B.track(B.Beam.from_inputs(beams[0]), Ls[0], 2, vws[0], seed=int(seeds[0]), moments=vmom[0])
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for v in range(nvar):
+        B.track(vb[v], Ls[v], turns, vws[v], seed=int(seeds[v]), moments=vmom[v])
+    e.record()
+    torch.cuda.synchronize()
+    ts = a.elapsed_time(e)
     same = True
     for v in range(nvar):
         h = vb[v].host()
@@ -403,19 +598,16 @@ def batch_bench(args):
         same &= bool(np.array_equal(res_b["z"][:, sl][:, o1], h["z"][:, o2]) and
                      np.array_equal(res_b["lost_at"][sl][o1], h["lost_at"][o2]))
     steps = element_steps(lats[0], turns, int(seg[-1]), res_b["lost_at"], 0)
-    out = {"metric": "particle\u00b7element steps/s (batched ring scan)",
-           "value": steps / (tb / 1e3), "unit": "particle\u00b7element steps/s",
-           "n_gpus": 1, "steps": turns, "warmup": 1, "ms_per_step": tb / turns,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic",
+    out = {"metric": "particle·element steps/s (batched ring scan)",
+           "value": steps / (tb / 1e3), "unit": STEP_UNIT, "steps": turns, "warmup": 1,
+           "ms_per_step": tb / turns, "higher_is_better": True, "dtype": "f64",
            "config": {"workload": f"batched scan: {nvar} ring variants, {int(seg[-1])} particles "
                                   f"(log-uniform 1e3-1e5 per variant), {turns} turns, moments "
-                                  "every turn", "tuning": tune, "autotune_s": round(t_tune, 2)},
+                                  "every turn, one graph-captured persistent launch sequence",
+                      "tuning": tune, "autotune_s": round(t_tune, 2)},
            "sequential": {"value": steps / (ts / 1e3), "ms": ts},
            "batched_ms": tb, "speedup_vs_sequential": ts / tb,
            "variants_identical_to_sequential": same}
-    # the batched launch is bound by FP64 arithmetic, as the ring's run kernel
-    # (same elements): its FP64 flops per element step over the whole job
     fl = FP64_FLOP_PER_STEP["ring"] * steps
     ach = fl / (tb / 1e3) / 1e12
     out["roofline"] = {"bound": "alu", "kernel": "trk::k_batch (persistent; whole batched call)",
@@ -423,16 +615,16 @@ def batch_bench(args):
                        "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
                        "fp64_flops_per_element_step": FP64_FLOP_PER_STEP["ring"]}
     if not args.no_cpu_baseline:
-        # the oracle on variant 0 (its own sextupoles, beam and key), all turns
-        cv, cdt, cores = cpu_baseline(lats[0], dict(seed=1000), turns, 1e9, int(sizes[0]),
-                                      seed=int(seeds[0]))
-        out["cpu_baseline"] = {"value": cv, "unit": "particle\u00b7element steps/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": f"variant 0 ({int(sizes[0])} particles), {turns} turns, "
-                                         f"{cdt:.1f} s wall"}
-    print(json.dumps(out))
+        log("batch: CPU oracle ...")
+        v0 = int(np.argmin(sizes))
+        out["cpu_baseline"] = cpu_baseline(lats[v0], dict(n=int(sizes[v0]), seed=1000 + v0),
+                                           turns, 1e9, int(sizes[v0]), min(int(sizes[v0]), 500),
+                                           seed=int(seeds[v0]),
+                                           what=f"batched scan, variant {v0}")
+    return out
 
 
+# ------------------------------------------------------------------ loss reorderings
 def compact_bench(args):
     """The paper's comparison of loss reorderings (Sec. 2.5): time the stable
     reordering, the paper's sparse swap and the sort by key on 4e6 particles
@@ -440,7 +632,6 @@ def compact_bench(args):
     import torch
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     n = int(args.particles or 4_000_000)
     reps = args.steps or 10
     d = inputs.gaussian_beam(n, seed=0)
@@ -477,15 +668,151 @@ def compact_bench(args):
     ratios = {f"{f:g}": {"sort/swap": ms[(f, "sort")] / ms[(f, "swap")],
                          "stable/swap": ms[(f, "stable")] / ms[(f, "swap")]}
               for f in (0.005, 0.05, 0.1, 0.5)}
-    out = {"metric": "loss reordering time per call (ms), stable reordering at 5 % loss",
-           "value": ms[(0.05, "stable")], "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1,
-           "ms_per_step": ms[(0.05, "stable")], "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": f"loss reordering of {n:.0e} particles with losses at random "
-                                  "slots (stable, the paper's sparse swap, sort by key)",
-                      "particles": n},
-           "table": rows, "ratios": ratios, "roofline": None}
-    print(json.dumps(out))
+    return {"metric": "loss reordering time per call (ms), stable reordering at 5 % loss",
+            "value": ms[(0.05, "stable")], "unit": "ms", "steps": reps, "warmup": 1,
+            "ms_per_step": ms[(0.05, "stable")], "higher_is_better": False, "dtype": "int64",
+            "config": {"workload": f"loss reordering of {n:.0e} particles with losses at random "
+                                   "slots (stable, the paper's sparse swap, sort by key)",
+                       "particles": n},
+            "table": rows, "ratios": ratios, "roofline": None}
+
+
+# ------------------------------------------------------------------ sweeps and ablations
+def sweep_bench(args):
+    """Steps/s against the particle count (the paper's speed-up against N,
+    Sec. 3): the bunch compressor pass and the FODO channel with whole passes
+    fused, N = 1e4 ... 1e7."""
+    rows = []
+    for n in (10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000, 10_000_000):
+        for wl, passes in (("bc", 1), ("roof", 10)):
+            r = track_workload(wl, args, n=n, steps=5, warm=2, passes=passes, fusion=0,
+                               cpu=False, roof=False)
+            rows.append({"workload": wl, "particles": n, "value": r["value"],
+                         "ms_per_step": round(r["ms_per_step"], 4),
+                         "run_kernel_us": round(r["kernel_time"]["run"]["avg_us"], 2)})
+            log(json.dumps(rows[-1]))
+    return {"metric": "particle·element steps/s against N", "unit": STEP_UNIT,
+            "config": {"workload": "bunch compressor (one pass per step) and FODO channel (10 "
+                                   "passes per step, whole passes fused), N from 1e4 to 1e7"},
+            "table": rows}
+
+
+def ablation_bench(args):
+    """Moment reductions (Sec. 2.4): the ring at 1e6 particles, 32 turns, one
+    turn per launch, with no moments, with the per-turn moments fused into
+    the run kernel (shifted one-pass rows), and with a separate two-pass
+    moments call after every turn."""
+    import torch
+    from paper_1710_07350_amd import binding as B
+    from paper_1710_07350_amd import inputs
+    n, turns = int(args.particles or 1_000_000), 32
+    lat = inputs.ring_lattice(seed=0)
+    L = B.Lattice(lat)
+    src = B.Beam.from_inputs(inputs.gaussian_beam(n, seed=0))
+    ws = B.Workspace(n)
+    mom = torch.zeros((turns, 28), dtype=torch.float64, device="cuda")
+
+    def run(mode):
+        b = src.clone()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record()
+        if mode == "separate":
+            for t in range(turns):
+                B.track(b, L, 1, ws, seed=7, first_pass=t)
+                mom[t].copy_(B.moments(b, ws))
+        else:
+            B.track(b, L, turns, ws, seed=7, passes_per_launch=1,
+                    moments=mom if mode == "fused" else None)
+        e.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(e)
+
+    out = {}
+    for mode in ("none", "fused", "separate", "none", "fused", "separate"):
+        out.setdefault(mode, []).append(run(mode))
+    res = {m: float(np.median(v)) / turns for m, v in out.items()}
+    return {"metric": "ms per ring turn (1e6 particles) by moment-reduction scheme", "unit": "ms",
+            "config": {"workload": f"storage ring, {n:.0e} particles, {turns} turns, one turn "
+                                   "per launch"},
+            "ms_per_turn": res,
+            "moment_cost_ms_per_turn": {"fused": res["fused"] - res["none"],
+                                        "separate": res["separate"] - res["none"]}}
+
+
+def ceilings_bench(args):
+    """Measured copy, read and FP64 FMA ceilings of the box, beside the
+    datasheet peaks: the library's probe kernels over 1 GiB arrays and FP64
+    fma chains, median of 20 launches timed with HIP events."""
+    import torch
+    from paper_1710_07350_amd import binding as B
+
+    def median_ms(fn, reps=20):
+        st = torch.cuda.current_stream()
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            b.synchronize()
+            t.append(a.elapsed_time(b))
+        return float(np.median(t))
+
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for blocks in (4096, 16384, 65536, 131072):
+        ms = median_ms(lambda: B.probe_stream(src, dst, 0, blocks))
+        out[f"copy_TBps_{blocks}"] = round(2 * 8 * n / (ms * 1e-3) / 1e12, 3)
+        ms = median_ms(lambda: B.probe_stream(src, dst, 2, blocks))
+        out[f"copy_nt_TBps_{blocks}"] = round(2 * 8 * n / (ms * 1e-3) / 1e12, 3)
+        ms = median_ms(lambda: B.probe_stream(src, dst, 1, blocks))
+        out[f"read_TBps_{blocks}"] = round(8 * n / (ms * 1e-3) / 1e12, 3)
+    iters = 4096
+    for blocks in (2048, 8192):
+        buf = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+        ms = median_ms(lambda: B.probe_fma(buf, iters, blocks))
+        out[f"fp64_fma_TFLOPs_{blocks}"] = round(blocks * 256 * 8 * iters * 2 / (ms * 1e-3) / 1e12,
+                                                 2)
+    out["copy_TBps"] = max(v for k, v in out.items() if k.startswith("copy_"))
+    out["read_TBps"] = max(v for k, v in out.items() if k.startswith("read_"))
+    out["fp64_TFLOPs"] = max(v for k, v in out.items() if k.startswith("fp64_fma_"))
+    return {"metric": "measured ceilings", "config": {"workload": "copy/read 1 GiB, FP64 fma"},
+            "ceilings": out}
+
+
+def copycal_bench(args):
+    """A plain device-to-device copy of known size (three times), for
+    calibrating the HBM byte counters rocprofv3 reports per dispatch."""
+    import torch
+    n = args.mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"metric": "copy calibration", "config": {"workload": f"copy {args.mib} MiB x 3"}}
+
+
+# ------------------------------------------------------------------ main
+def contract(out, n_gpus=1):
+    """The fields every printed line carries."""
+    base = {"metric": out.get("metric"), "value": out.get("value"), "unit": out.get("unit"),
+            "n_gpus": n_gpus, "steps": out.get("steps"), "warmup": out.get("warmup"),
+            "ms_per_step": out.get("ms_per_step"),
+            "higher_is_better": out.get("higher_is_better", True), "scaling": "weak",
+            "vs_baseline": None, "dtype": out.get("dtype"), "data": "synthetic"}
+    for k, v in out.items():
+        if k not in base:
+            base[k] = v
+    return base
 
 
 def main():
@@ -495,201 +822,49 @@ def main():
               "library tracks a beam on one device (a beam sharded by particle index over "
               "several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "surr":
-        return surrogate_bench(args)
-    if args.workload == "batch":
-        return batch_bench(args)
-    if args.workload == "compact":
-        return compact_bench(args)
     import torch
-    from paper_1710_07350_amd import binding as B
-    from paper_1710_07350_amd import inputs
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wl = args.workload
-    wake_mode = B.WAKE_FP32_MFMA if args.wake_mode == "fp32" else B.WAKE_FP64
+    single = {"surr": surrogate_bench, "batch": batch_bench, "compact": compact_bench,
+              "sweep": sweep_bench, "ablation": ablation_bench, "ceilings": ceilings_bench,
+              "copycal": copycal_bench}
+    if wl in single:
+        print(json.dumps(contract(single[wl](args))))
+        return
+    if wl != "bc" or args.headline_only:
+        print(json.dumps(contract(track_workload(wl, args))))
+        return
 
-    if wl in ("bc", "rfcw"):
-        lat = inputs.bc_lattice() if wl == "bc" else inputs.rfcw_lattice()
-        n = int(args.particles or 4_000_000)
-        beam_kw = dict(n=n, seed=0, chirp=inputs.BC_CHIRP)
-        p_ref, passes_per_step = inputs.BC_P0_EV, 1
-        steps = args.steps or 50
-        warm = args.warmup if args.warmup is not None else 5
-        fresh = True
-        cfg = {"workload": "linac bunch compressor: 4e6-particle chirped Gaussian beam, "
-                           "8 x (RF cavity + 1024-bin wake step) + 2nd-order chicane"
-                           if wl == "bc" else
-                           "linac bunch compressor with transverse wakes: 4e6-particle chirped "
-                           "Gaussian beam, 8 x (RF cavity + 1024-bin longitudinal and transverse "
-                           "wake steps) + 2nd-order chicane",
-               "particles": n, "elements_per_pass": len(lat),
-               "wake_convolution": "fp32-mfma" if wake_mode == B.WAKE_FP32_MFMA else "fp64",
-               "batch": "fresh device-resident beam per step"}
-        sample = (n, 10)
-    elif wl == "ring":
-        lat = inputs.ring_lattice(seed=0)
-        n = int(args.particles or 1_000_000)
-        beam_kw = dict(n=n, seed=0)
-        if args.sigma_scale != 1.0:
-            beam_kw["sigmas"] = tuple(args.sigma_scale * v for v in inputs.BEAM_SIGMAS)
-        p_ref, passes_per_step = 1e9, 1
-        steps = args.steps or 20
-        warm = args.warmup if args.warmup is not None else 2
-        fresh = False
-        cfg = {"workload": "storage ring: 1e6 particles, 40 cells of Yoshida-4 kick-drift "
-                           "quads and sector bends, random thin sextupoles, Philox radiation "
-                           "kick, elliptical aperture with compaction, moments every turn",
-               "particles": n, "elements_per_pass": len(lat), "turns_per_step": 1}
-        sample = (100_000, 40)
-    else:  # fodo / roof
-        lat = inputs.fodo_lattice(quad_order=args.quad_order)
-        n = int(args.particles or (10_000 if wl == "fodo" else 10_000_000))
-        beam_kw = dict(n=n, seed=0)
-        if args.sigma_scale != 1.0:
-            beam_kw["sigmas"] = tuple(args.sigma_scale * v for v in inputs.BEAM_SIGMAS)
-        p_ref = 1e9
-        passes_per_step = 10 if wl == "roof" else 100
-        steps = args.steps or 5
-        warm = args.warmup if args.warmup is not None else 1
-        fresh = True
-        cfg = {"workload": f"FODO channel: {n:.0e} particles, 10 cells (60 elements) per pass, "
-                           f"{passes_per_step} passes per step"
-                           + (", third-order quadrupole maps" if args.quad_order == 3 else ""),
-               "particles": n, "elements_per_pass": len(lat), "fusion_max_elements": args.fusion,
-               "quad_order": args.quad_order}
-        sample = (10_000, 100) if wl == "fodo" else (1_000_000, 10)
+    t_start = time.perf_counter()
+    head = track_workload("bc", args)
+    configs = {}
 
-    L = B.Lattice(lat)
-    d = inputs.gaussian_beam(**beam_kw)
-    template = B.Beam.from_inputs(d)
-    ws = B.Workspace(n)
-    # two timed regions of `steps` steps each: the first, without per-kernel
-    # events (an event between two kernels stalls the queue for a few us), gives
-    # the throughput; the second, with HIP events around every fused run on the
-    # same stream, gives the run kernel's average duration for the roofline
-    nb = (warm + 2 * steps) if fresh else 1
-    beams = []
-    for _ in range(nb):
-        b = B.Beam.__new__(B.Beam)
-        b.n = n
-        b.z = template.z.clone()
-        b.id = template.id.clone()
-        b.lost_at = template.lost_at.clone()
-        b.n_alive = template.n_alive.clone()
-        beams.append(b)
-    mom = torch.zeros((max(passes_per_step, 1), 28), dtype=torch.float64, device="cuda")
-    use_mom = wl == "ring"
-    stream = torch.cuda.current_stream()
+    def nested(name, fn):
+        t0 = time.perf_counter()
+        log(f"--- {name}")
+        try:
+            configs[name] = fn()
+        except Exception as exc:       # one failing extra must not hide the headline
+            configs[name] = {"error": f"{type(exc).__name__}: {exc}"}
+        configs[name]["wall_s"] = round(time.perf_counter() - t0, 1)
+        torch.cuda.empty_cache()
 
-    def one_step(i):
-        b = beams[i if fresh else 0]
-        fp = 0 if fresh else i * passes_per_step
-        B.track(b, L, passes_per_step, ws, seed=7, first_pass=fp, p_ref=p_ref,
-                moments=mom if use_mom else None, wake_mode=wake_mode,
-                max_elems_per_launch=args.fusion, stream=stream)
-
-    def timed(i0, i1):
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record(stream)
-        for i in range(i0, i1):
-            one_step(i)
-        t1.record(stream)
-        torch.cuda.synchronize()
-        return t0.elapsed_time(t1)
-
-    for i in range(warm):
-        one_step(i)
-    torch.cuda.synchronize()
-    ms_total = timed(warm, warm + steps)
-    B.profile_enable(True)
-    timed(warm + steps, warm + 2 * steps)
-    run_ms, run_launches = B.profile_read(0)
-    B.profile_enable(False)
-
-    def steps_of(i0, i1):
-        """exact particle-element steps of steps [i0, i1)"""
-        if fresh:
-            tot = 0.0
-            for i in range(i0, i1):
-                la = beams[i].lost_at.cpu().numpy()
-                tot += element_steps(lat, passes_per_step, n, la, 0)
-            return tot
-        # a continuing beam: count survivors per turn from the loss records
-        la = beams[0].lost_at.cpu().numpy()
-        first = i0 * passes_per_step
-        last = i1 * passes_per_step
-        nel = len(lat)
-        lp = la >> 32
-        lost = la >= 0
-        alive_then = float((la < 0).sum()) + float((lost & (lp >= last)).sum())
-        tot = alive_then * (last - first) * nel
-        inside = lost & (lp >= first) & (lp < last)
-        pl = lp[inside] - first
-        el = la[inside] & 0xFFFFFFFF
-        return tot + float((pl * nel + el + 1).sum())
-
-    total_steps = steps_of(warm, warm + steps)
-    value = total_steps / (ms_total / 1e3)
-    prof_steps = steps_of(warm + steps, warm + 2 * steps)
-
-    # roofline of the dominant kernel (fused element run)
-    plan = launches_of(lat, 16, args.fusion)
-    bytes_per_pass = 0.0
-    launches_per_pass = 0.0
-    for j, (e0, e1, npass) in enumerate(plan):
-        nxt = plan[(j + 1) % len(plan)][0] if len(plan) > 1 else None
-        next_wake = nxt is not None and lat[nxt].kind in WAKES and (j + 1 < len(plan))
-        per = run_mask_bytes(lat, e0, e1, moments=(use_mom and e1 == len(lat)),
-                             next_wake=next_wake)
-        if npass > 1:
-            bytes_per_pass += per / npass
-            launches_per_pass += 1.0 / npass
-        else:
-            bytes_per_pass += per
-            launches_per_pass += 1.0
-    alive_mean = prof_steps / (steps * passes_per_step * len(lat))
-    alg_bytes_per_launch = alive_mean * bytes_per_pass / launches_per_pass
-    avg_ms = run_ms / max(run_launches, 1)
-    achieved = alg_bytes_per_launch / (avg_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "kernel": "trk::k_run (fused element run)",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC_PER_LAUNCH.get((wl, args.fusion)) if args.quad_order == 2 else None,
-            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": run_launches,
-            "alg_bytes_per_launch": round(alg_bytes_per_launch)}
-    # a launch whose FP64 work per byte exceeds the machine balance is bound by
-    # the FP64 vector units: report it against their peak instead
-    fkey = wl
-    if wl in ("fodo", "roof"):
-        fkey = "fodo3" if args.quad_order == 3 else "fodo"
-    fpp = FP64_FLOP_PER_STEP.get(fkey)
-    if fpp is not None:
-        steps_per_launch = prof_steps / max(run_launches, 1)
-        flops = fpp * steps_per_launch
-        if flops / max(alg_bytes_per_launch, 1.0) > FP64_PEAK_TFLOPS / (HBM_PEAK_GBS / 1e3):
-            ach = flops / (avg_ms / 1e3) / 1e12
-            roof.update({"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                         "traffic": None, "alg_flops_per_launch": flops,
-                         "fp64_flops_per_element_step": fpp})
-
-    out = {"metric": "particle·element steps/s (FP64 tracking)", "value": value,
-           "unit": "particle·element steps/s", "n_gpus": 1, "steps": steps,
-           "warmup": warm, "ms_per_step": ms_total / steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": cfg, "roofline": roof}
-    if not args.no_cpu_baseline:
-        sn, sp = sample
-        cv, cdt, cores = cpu_baseline(lat, beam_kw, sp, p_ref, sn)
-        out["cpu_baseline"] = {"value": cv, "unit": "particle·element steps/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": f"{sn} particles of the same workload, {sp} passes, "
-                                         f"{cdt:.1f} s wall"}
-    print(json.dumps(out))
+    sub = argparse.Namespace(**{**vars(args), "steps": None, "warmup": None, "particles": None,
+                                "fusion": 0, "turns": None})
+    nested("fodo_1e4", lambda: track_workload("fodo", sub, steps=5, warm=1))
+    nested("roof_1e7_one_element_per_launch",
+           lambda: track_workload("roof", sub, steps=3, warm=1, fusion=1))
+    nested("roof_1e7_whole_pass", lambda: track_workload("roof", sub, steps=3, warm=1, fusion=0))
+    nested("ring_1e6_1000_turns", lambda: track_workload("ring", sub))
+    nested("batch_256_200_turns", lambda: batch_bench(sub))
+    nested("bc_4e7", lambda: track_workload("bc", sub, n=40_000_000, steps=5, warm=1, cpu=False))
+    nested("n_sweep", lambda: sweep_bench(sub))
+    nested("moment_reductions", lambda: ablation_bench(sub))
+    nested("surrogate", lambda: surrogate_bench(sub))
+    head["configs"] = configs
+    head["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+    print(json.dumps(contract(head)))
 
 
 if __name__ == "__main__":

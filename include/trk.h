@@ -476,10 +476,11 @@ int trk_probe_fma(double *out_dev, int32_t iters, int32_t blocks, void *stream);
 /* ------------------------------------------------------------------ misc */
 const char *trk_status_string(int status);
 const char *trk_last_error(void);
-/* per-kernel-class device time (ms) and launch count accumulated with HIP
- * events while enabled; class 0 = fused element run, class 1 = surrogate
- * network inference, class 2 = wake histogram, class 3 = wake convolution
- * (inside trk_track).  trk_profile_enable: `on` is a bit mask of the classes
+/* per-kernel-class device time (ms) and launch count accumulated while
+ * enabled, from start and stop events that each timed kernel's own dispatch
+ * records (hipExtLaunchKernel: no event packet between kernels); class 0 =
+ * fused element run, class 1 = surrogate network inference, class 2 = wake
+ * histogram, class 3 = wake convolution (inside trk_track).  trk_profile_enable: `on` is a bit mask of the classes
  * to time (bit c = class c; 0 stops timing); a nonzero mask also clears the
  * accumulated figures. */
 int trk_profile_enable(int32_t on);

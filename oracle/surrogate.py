@@ -29,6 +29,8 @@ What is computed here, in the order the functions follow:
                     2x2 (plus dispersion column) block of R;
 * ``gate_constants``/``gate``  the admission test;
 * ``forward`` / ``loss_and_grad``  the network and its exact gradient;
+* ``loss_and_grad_bf16``  the gradient with the bfloat16 rounding points of
+                    a matrix-core training step;
 * ``adam``          one Adam step (Kingma & Ba, ICLR 2015, Algorithm 1) in
                     FP64 arithmetic on FP32-stored state.
 """
@@ -171,6 +173,46 @@ def loss_and_grad(p, u, t, round_weights: bool = True):
     g["b1"] = dA1.sum(0)
     flat = np.concatenate([g[name].reshape(-1) for name, _ in SHAPES])
     return loss, flat
+
+
+def loss_and_grad_bf16(p, u, t, mode: str = "bf16x2"):
+    """Loss and gradient with the rounding points of a bfloat16 matrix-core
+    training step, FP64 arithmetic everywhere else:
+
+      forward in `mode` (activations entering products as bfloat16 or as the
+      sum of two), output error dO = bf16((o - t) 2/(6n)) with 2/(6n) taken
+      in binary32;
+      dh3 = dO W4;  dA_l = bf16(dh_l silu'(a_l));  dh_{l-1} = dh_l + dA_l W_l;
+      weight gradients dA_l^T bf16(h_{l-1}) (layer 1: bf16(u)), bias
+      gradients sum_rows dA_l, output layer dO^T bf16(h3) and sum_rows dO.
+
+    Returns (loss, flat gradient, parts) where parts holds the rounded
+    operands and the values before rounding (for error bounds)."""
+    o, c = forward(p, u, mode, True, cache=True)
+    W = c["W"]
+    n = o.shape[0]
+    scale = float(np.float32(2.0) / np.float32(6.0 * n))
+    d = o - t
+    loss = float((d * d).sum() / (6.0 * n))
+    pre = {"dO": d * scale}
+    rnd = {"dO": bf16_rne(pre["dO"].astype(np.float32)).astype(np.float64)}
+    dh = {3: rnd["dO"] @ W["W4"]}
+    for layer, wname in ((3, "W3"), (2, "W2"), (1, None)):
+        key = f"dA{layer}"
+        pre[key] = dh[layer] * dsilu(c[f"a{layer}"])
+        rnd[key] = bf16_rne(pre[key].astype(np.float32)).astype(np.float64)
+        if wname is not None:
+            dh[layer - 1] = dh[layer] + rnd[key] @ W[wname]
+    for name, src in (("u", c["u"]), ("h1", c["h1"]), ("h2", c["h2"]), ("h3", c["h3"])):
+        pre[name] = src
+        rnd[name] = bf16_rne(src.astype(np.float32)).astype(np.float64)
+    g = {"W4": rnd["dO"].T @ rnd["h3"], "b4": rnd["dO"].sum(0),
+         "W3": rnd["dA3"].T @ rnd["h2"], "b3": rnd["dA3"].sum(0),
+         "W2": rnd["dA2"].T @ rnd["h1"], "b2": rnd["dA2"].sum(0),
+         "W1": rnd["dA1"].T @ rnd["u"], "b1": rnd["dA1"].sum(0)}
+    flat = np.concatenate([g[name].reshape(-1) for name, _ in SHAPES])
+    parts = dict(pre=pre, rnd=rnd, dh=dh, o=o, cache=c)
+    return loss, flat, parts
 
 
 # ---------------------------------------------------------------- Adam

@@ -21,6 +21,8 @@
 using namespace trk;
 
 namespace trk {
+thread_local KernelEvents g_kernel_events{nullptr, nullptr};
+
 namespace host {
 
 thread_local std::string g_err;
@@ -100,8 +102,12 @@ struct Prof {
   int64_t launches[4] = {0, 0, 0, 0};
 } g_prof;
 
+// While class cls is timed, the launch's one kernel goes out through the
+// extended launch with a pair of events that its dispatch packet records
+// (TRK_LAUNCH); a launch that enqueued nothing leaves the pair unused.
 template <class F>
 hipError_t profiled(int cls, hipStream_t st, F &&launch) {
+  (void)st;
   bool on;
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -112,10 +118,19 @@ hipError_t profiled(int cls, hipStream_t st, F &&launch) {
   hipError_t e = hipEventCreate(&a);
   if (e != hipSuccess) return e;
   e = hipEventCreate(&b);
-  if (e != hipSuccess) return e;
-  (void)hipEventRecord(a, st);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return e;
+  }
+  g_kernel_events = KernelEvents{a, b};
   e = launch();
-  (void)hipEventRecord(b, st);
+  const bool used = g_kernel_events.start == nullptr;
+  g_kernel_events = KernelEvents{nullptr, nullptr};
+  if (!used || e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return e;
+  }
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.ev[cls].push_back({a, b});
   return e;
@@ -711,12 +726,16 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   // launch plan
   std::vector<Launch> plan;
   const int max_e = opts->max_elems_per_launch > 0 ? opts->max_elems_per_launch : nelem;
+  // whole passes per launch: particles lost in one launch are compacted
+  // away before the next (a launch of several passes costs far more than a
+  // compaction, and later launches then skip the lost slots' waves)
+  const bool whole_passes = !lat->has_wake && max_e >= nelem;
   auto nvar_in = [&](int e0, int e1) {
     int c = 0;
     for (int e = e0; e < e1; ++e) c += lat->vslot[e] >= 0;
     return c;
   };
-  if (!lat->has_wake && max_e >= nelem) {
+  if (whole_passes) {
     int ppl = opts->passes_per_launch > 0 ? opts->passes_per_launch : 16;
     ppl = std::min(ppl, mom ? kMomPassesMax : kMaxPassesPerLaunch);
     if (lat->nvar > 0) ppl = std::min(ppl, std::max(1, kMaxVar / lat->nvar));
@@ -749,8 +768,8 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
   int prev_mm_n = 0;  // > 0: the previous launch left (min, max) partials
   // Compaction is lazy: particles lost in a run keep their slots (the run
   // kernel skips them by their loss record) until a histogram needs the
-  // alive set packed, or the call ends.  The final layout does not depend on
-  // when compaction runs.
+  // alive set packed, the next launch of a whole-pass plan begins, or the
+  // call ends.  The final layout does not depend on when compaction runs.
   bool dirty = false;
   // A run that changes neither s nor the alive set (RF, wake, transverse-wake
   // and random energy kicks, markers; no apertures) bins the histogram of a
@@ -933,6 +952,11 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
               "moments");
     }
     dirty = dirty || any_aper;
+    if (dirty && whole_passes && li + 1 < plan.size()) {
+      HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
+              "compact");
+      dirty = false;
+    }
   }
   if (dirty)
     HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),

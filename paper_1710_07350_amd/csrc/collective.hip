@@ -182,10 +182,10 @@ hipError_t launch_histogram(const double *s, const int64_t *n_alive, int64_t n_t
   const size_t lds = static_cast<size_t>(nsub) * per + (d ? 8 : 0);
   auto *du = reinterpret_cast<unsigned long long *>(dip);
   if (d)
-    hipLaunchKernelGGL(k_histogram<true>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
+    TRK_LAUNCH((k_histogram<true>), dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
                        n_alive, n_total, mm_part, mm_n, nbins, nsub, counts, du, range);
   else
-    hipLaunchKernelGGL(k_histogram<false>, dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
+    TRK_LAUNCH((k_histogram<false>), dim3(grid), dim3(kHistThreads), lds, st, s, x, y,
                        n_alive, n_total, mm_part, mm_n, nbins, nsub, counts, du, range);
   return hipGetLastError();
 }
@@ -344,10 +344,10 @@ hipError_t launch_conv(const void *src, int nbins, int ncopy, const double *rang
                        hipStream_t st) {
   const dim3 grid((nbins + kTile - 1) / kTile, kTr ? 2 : 1);
   if (mode == TRK_WAKE_FP32_MFMA)
-    hipLaunchKernelGGL(k_conv_mfma<kTr>, grid, dim3(64 * kConvWaves), 0, st, src, nbins, ncopy,
+    TRK_LAUNCH((k_conv_mfma<kTr>), grid, dim3(64 * kConvWaves), 0, st, src, nbins, ncopy,
                        range, tau0, omega, v, wake_par, zbuf, zn);
   else
-    hipLaunchKernelGGL(k_conv_fp64<kTr>, grid, dim3(kTile), 0, st, src, nbins, ncopy, range, tau0,
+    TRK_LAUNCH((k_conv_fp64<kTr>), grid, dim3(kTile), 0, st, src, nbins, ncopy, range, tau0,
                        omega, v, wake_par, zbuf, zn);
   return hipGetLastError();
 }

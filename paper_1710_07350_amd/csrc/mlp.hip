@@ -607,9 +607,9 @@ hipError_t launch_surr_infer(const MlpDev &m, const SurrDev &c, const BeamPtrs6 
   const int64_t grid = (n_total + kRows - 1) / kRows;
   if (grid == 0) return hipSuccess;
   if (x2)
-    hipLaunchKernelGGL(k_surr_infer<1>, dim3(grid), dim3(kBlock), 0, st, m, c, b, adm, n_adm);
+    TRK_LAUNCH((k_surr_infer<1>), dim3(grid), dim3(kBlock), 0, st, m, c, b, adm, n_adm);
   else
-    hipLaunchKernelGGL(k_surr_infer<0>, dim3(grid), dim3(kBlock), 0, st, m, c, b, adm, n_adm);
+    TRK_LAUNCH((k_surr_infer<0>), dim3(grid), dim3(kBlock), 0, st, m, c, b, adm, n_adm);
   return hipGetLastError();
 }
 

@@ -293,10 +293,10 @@ void launch_ppt_nt(const RunArgs &a, int grid, hipStream_t st) {
   // a run-binned histogram keeps its counts in LDS
   const size_t lds = a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
   switch (a.ppt) {
-    case 8: hipLaunchKernelGGL((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
-    case 2: hipLaunchKernelGGL((k_run<kFeat, false, 2, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
-    default: hipLaunchKernelGGL((k_run<kFeat, false, 1, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    case 8: TRK_LAUNCH((k_run<kFeat, false, 8, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    case 4: TRK_LAUNCH((k_run<kFeat, false, 4, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    case 2: TRK_LAUNCH((k_run<kFeat, false, 2, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
+    default: TRK_LAUNCH((k_run<kFeat, false, 1, kLong, kNT>), dim3(grid), dim3(kBlock), lds, st, a); break;
   }
 }
 
@@ -312,9 +312,9 @@ template <uint32_t kFeat>
 void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
   if (a.mom) {
     if (a.ppt >= 2)
-      hipLaunchKernelGGL((k_run<kFeat, true, 2, false>), dim3(grid), dim3(kBlock), 0, st, a);
+      TRK_LAUNCH((k_run<kFeat, true, 2, false>), dim3(grid), dim3(kBlock), 0, st, a);
     else
-      hipLaunchKernelGGL((k_run<kFeat, true, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
+      TRK_LAUNCH((k_run<kFeat, true, 1, false>), dim3(grid), dim3(kBlock), 0, st, a);
   } else if constexpr (light(kFeat)) {
     if constexpr (longit_ok(kFeat)) {
       if (a.longit) {
@@ -327,9 +327,9 @@ void launch_feat(const RunArgs &a, int grid, hipStream_t st) {
     // heavy runs: one or two particles per thread
     const size_t lds = a.hist_out != nullptr ? sizeof(uint32_t) * a.hist_nbins : 0;
     if (a.ppt >= 2)
-      hipLaunchKernelGGL((k_run<kFeat, false, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
+      TRK_LAUNCH((k_run<kFeat, false, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
     else
-      hipLaunchKernelGGL((k_run<kFeat, false, 1, false>), dim3(grid), dim3(kBlock), lds, st, a);
+      TRK_LAUNCH((k_run<kFeat, false, 1, false>), dim3(grid), dim3(kBlock), lds, st, a);
   }
 }
 

@@ -1,6 +1,7 @@
 // trk_internal.h -- device records, kernel arguments and launch helpers
 // shared by the HIP translation units of libtrk.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -8,6 +9,26 @@
 #include "../../include/trk.h"
 
 namespace trk {
+
+// Start and stop events for the next kernel this thread launches through
+// TRK_LAUNCH (set by the profiling wrapper, consumed by that one launch).
+// The extended launch has the dispatch packet itself record the kernel's
+// start and end, so no event packet sits between two kernels of the stream.
+struct KernelEvents {
+  hipEvent_t start, stop;
+};
+extern thread_local KernelEvents g_kernel_events;
+
+#define TRK_LAUNCH(kernel, grid, block, lds, st, ...)                                           \
+  do {                                                                                        \
+    if (::trk::g_kernel_events.start != nullptr) {                                            \
+      const ::trk::KernelEvents ev_ = ::trk::g_kernel_events;                                 \
+      ::trk::g_kernel_events = ::trk::KernelEvents{nullptr, nullptr};                         \
+      hipExtLaunchKernelGGL(kernel, grid, block, lds, st, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+    } else {                                                                                  \
+      hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                          \
+    }                                                                                         \
+  } while (0)
 
 constexpr int kBlock = 256;
 // copies of the counts a run-binned histogram merges into (spreads the

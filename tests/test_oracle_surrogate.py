@@ -154,6 +154,79 @@ def test_bf16_modes_are_close_to_exact():
 
 
 # ---------------------------------------------------------------- Adam
+def _bf16_t(x):
+    return torch.from_numpy(S.bf16_rne(x.detach().numpy().astype(np.float32)).astype(np.float64))
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity forward; the incoming gradient rounded to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return _bf16_t(g)
+
+
+class _Lin(torch.autograd.Function):
+    """x W^T + b with the input entering as bfloat16 x2 (forward) and as one
+    bfloat16 in the weight gradient."""
+
+    @staticmethod
+    def forward(ctx, h, W, b):
+        x = torch.from_numpy(S._mfma_input(h.detach().numpy(), "bf16x2"))
+        ctx.save_for_backward(_bf16_t(h), W)
+        return x @ W.T + b
+
+    @staticmethod
+    def backward(ctx, g):
+        hb, W = ctx.saved_tensors
+        return g @ W, g.T @ hb, g.sum(0)
+
+
+def test_bf16_emulated_gradient_matches_autograd_with_rounding_hooks():
+    """The rounding points of loss_and_grad_bf16 re-expressed as autograd
+    functions (round the gradient at each pre-activation and at the output,
+    bfloat16 inputs in the weight gradients): torch derives the chain and the
+    skip sums itself; the two agree to summation order."""
+    p = S.init_params(5)
+    P = S.unpack(p)
+    rng = np.random.default_rng(15)
+    for k in ("b1", "b2", "b3"):
+        P[k][...] = rng.uniform(-0.3, 0.3, P[k].shape).astype(np.float32)
+    n = 256
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32).astype(np.float64)
+    u[:, S.S_COORD] = 0.0
+    t = rng.standard_normal((n, 6)) * 0.2
+    t[:, S.D_COORD] = 0.0
+    loss, g, parts = S.loss_and_grad_bf16(p, u, t)
+    W = {k: torch.from_numpy(v.copy()).requires_grad_(True) for k, v in S.weights(p).items()}
+    ut = torch.from_numpy(u)
+    a1 = _RoundGrad.apply(_Lin.apply(ut, W["W1"], W["b1"]))
+    h1 = torch.nn.functional.silu(a1)
+    a2 = _RoundGrad.apply(_Lin.apply(h1, W["W2"], W["b2"]))
+    h2 = h1 + torch.nn.functional.silu(a2)
+    a3 = _RoundGrad.apply(_Lin.apply(h2, W["W3"], W["b3"]))
+    h3 = h2 + torch.nn.functional.silu(a3)
+    o = _RoundGrad.apply(_Lin.apply(h3, W["W4"], W["b4"]))
+    c = float(np.float32(2.0) / np.float32(6.0 * n)) / 2.0
+    (((o - torch.from_numpy(t)) ** 2).sum() * c).backward()
+    assert loss == pytest.approx(float(((o.detach().numpy() - t) ** 2).sum() / (6.0 * n)), rel=1e-14)
+    G = S.unpack(g)
+    for name, _ in S.SHAPES:
+        ref = W[name].grad.numpy()
+        diff = np.abs(G[name] - ref)
+        scale = np.abs(ref).max()
+        assert (diff <= 1e-12 * scale).mean() > 0.999, name
+        assert diff.max() <= 2.0 ** -7 * scale, name
+    # the rounding is felt: the emulated gradient is not the exact one
+    _, gx = S.loss_and_grad(p, u, t)
+    rel = np.linalg.norm(g - gx) / np.linalg.norm(gx)
+    assert 1e-5 < rel < 1e-2
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(11)
     w = rng.standard_normal(1000).astype(np.float32)
@@ -473,3 +546,85 @@ def test_sampler_draws_are_uniform_and_independent(orc):
     # other seeds and candidates beyond 2^32 give other points
     assert not np.array_equal(S.draw(orc, sw, 5, 7), S.draw(orc, sw, 6, 7))
     assert not np.array_equal(S.draw(orc, sw, 5, 7), S.draw(orc, sw, 5, 7 + 2 ** 32))
+
+
+# ---------------------------------------------------------------- error bounds
+def _f32_network(p, u, t, mode):
+    """A binary32 evaluation with the device's structure: bfloat16 operands
+    (activations split hi + lo in bf16x2 mode), binary32 products and sums,
+    binary32 SiLU from exp2 and a reciprocal, the skip path read back as
+    hi + lo; then the backward with the same rounding points as the oracle's
+    emulation.  Returns (o, flat gradient)."""
+    f32 = np.float32
+    W = {k: v.astype(f32) for k, v in S.weights(p).items()}
+
+    def split(h):
+        hi = S.bf16_rne(h)
+        lo = S.bf16_rne((h - hi).astype(f32))
+        return hi, lo
+
+    def mm(h, Wm):
+        hi, lo = split(h)
+        if mode == "bf16x2":
+            return (hi @ Wm.T + lo @ Wm.T).astype(f32)
+        return (hi @ Wm.T).astype(f32)
+
+    def sig(a):
+        return (f32(1.0) / (f32(1.0) + np.exp2(a * f32(-1.4426950408889634)))).astype(f32)
+
+    u32 = u.astype(f32)
+    a1 = (mm(u32, W["W1"]) + W["b1"]).astype(f32)
+    h1 = (a1 * sig(a1)).astype(f32)
+    a2 = (mm(h1, W["W2"]) + W["b2"]).astype(f32)
+    hi, lo = split(h1)
+    h2 = ((hi + lo) + a2 * sig(a2)).astype(f32)
+    a3 = (mm(h2, W["W3"]) + W["b3"]).astype(f32)
+    hi, lo = split(h2)
+    h3 = ((hi + lo) + a3 * sig(a3)).astype(f32)
+    o = (mm(h3, W["W4"]) + W["b4"]).astype(f32)
+    n = u.shape[0]
+    scale = f32(2.0) / f32(6.0 * n)
+    dO = S.bf16_rne(((o - t.astype(f32)) * scale).astype(f32))
+    dh = (dO @ W["W4"]).astype(f32)
+    g = {"W4": dO.T @ S.bf16_rne(h3), "b4": dO.sum(0)}
+    for l, a, hin in ((3, a3, h2), (2, a2, h1), (1, a1, u32)):
+        s = sig(a)
+        dA = S.bf16_rne((dh * (s * (f32(1.0) + a * (f32(1.0) - s)))).astype(f32))
+        g[f"W{l}"] = (dA.T @ S.bf16_rne(hin)).astype(f32)
+        g[f"b{l}"] = dA.sum(0, dtype=f32)
+        if l > 1:
+            dh = (dh + dA @ W[f"W{l}"]).astype(f32)
+    flat = np.concatenate([np.asarray(g[name], dtype=np.float64).reshape(-1) for name, _ in S.SHAPES])
+    return o.astype(np.float64), flat
+
+
+@pytest.mark.parametrize("lam", [None, 8.0])
+@pytest.mark.parametrize("mode", ["bf16x2", "bf16"])
+def test_mlp_bounds_cover_a_binary32_evaluation(mode, lam):
+    """The element-wise bounds the GPU tests use (tests/mlp_bounds.py) hold
+    for an independent binary32 evaluation on the CPU: every output and every
+    gradient element within its bound, and the bounds are not vacuous."""
+    import mlp_bounds as MB
+    p = S.init_params(8)
+    P = S.unpack(p)
+    rng = np.random.default_rng(18)
+    for k in ("b1", "b2", "b3"):
+        P[k][...] = rng.uniform(-0.3, 0.3, P[k].shape).astype(np.float32)
+    n = 512
+    u = rng.uniform(-1, 1, (n, 6)).astype(np.float32).astype(np.float64)
+    u[:, S.S_COORD] = 0.0
+    t = (rng.standard_normal((n, 6)) * 0.3).astype(np.float32).astype(np.float64)
+    t[:, S.D_COORD] = 0.0
+    o_ref, c = S.forward(p, u, mode, cache=True)
+    _, _, do = MB.forward_bound(c, mode, lam)
+    o32, g32 = _f32_network(p, u, t, mode)
+    err = np.abs(o32[:, :5] - o_ref[:, :5])
+    assert (err <= do[:, :5]).all(), (err / do[:, :5]).max()
+    _, g_emu, parts = S.loss_and_grad_bf16(p, u, t, mode)
+    bound = MB.grad_bound(parts, mode, n, lam)
+    gerr = np.abs(g32 - g_emu)
+    bad = gerr > bound
+    assert not bad.any(), (bad.sum(), np.nonzero(bad)[0][:10])
+    print(f"{mode} lam={lam}: output bound median {np.median(do[:, :5]):.2e} "
+          f"(error max {err.max():.2e}, max err/bound {(err / do[:, :5]).max():.3f}); "
+          f"gradient max err/bound {(gerr / np.maximum(bound, 1e-300)).max():.3f}")
