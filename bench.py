@@ -69,9 +69,9 @@ def parse():
     ap.add_argument("--workload", default="bc", choices=KINDS)
     ap.add_argument("--headline-only", action="store_true",
                     help="default workload: skip the nested configurations")
-    ap.add_argument("--epochs", type=int, default=20, help="surrogate training epochs")
+    ap.add_argument("--epochs", type=int, default=200, help="surrogate training epochs")
     ap.add_argument("--precision", default="bf16x2", choices=["bf16", "bf16x2"])
-    ap.add_argument("--margin", type=float, default=0.5, help="surrogate gate margin")
+    ap.add_argument("--margin", type=float, default=0.8, help="surrogate gate margin")
     ap.add_argument("--wake-mode", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fusion", type=int, default=0, help="max elements per launch (roof)")
     ap.add_argument("--quad-order", type=int, default=2, choices=[2, 3],

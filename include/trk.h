@@ -235,6 +235,7 @@ int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
 int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t workspace_bytes,
                 void *stream);
 
+
 /* compact_lost (Sec. 2.5): particles in [0, *n_alive) with lost_at >= 0 move
  * behind the survivors, ordered by lost_at descending, ties in their previous
  * order; survivors keep their order; *n_alive is decreased.  Particles at
@@ -308,8 +309,9 @@ int trk_track_batched(trk_batch *b, const trk_beam *beam, int32_t passes, int32_
  *   y = C + R z + D * o(N(z)),
  *
  * C = map(0) and R = Jacobian of the section map at the origin (central
- * differences of the tracker), N(z)_k = z_k / hw_k (box half widths; s is not
- * an input), D_k = RMS of the residual y - (C + R z) over the training pairs
+ * differences of the tracker), N(z)_k = z_k / sw_k (sw = the sampler's box,
+ * trk_surrogate_info.sample_half_width, which holds every admitted point, so
+ * admitted inputs fill [-1, 1]; s is not an input), D_k = RMS of the residual y - (C + R z) over the training pairs
  * (D = 0 for delta, which the section leaves unchanged), and o the residual
  * network 6 -> 256 -> 256 -> 256 -> 6: h1 = silu(W1 u + b1),
  * h2 = h1 + silu(W2 h1 + b2), h3 = h2 + silu(W3 h2 + b3), o = W4 h3 + b4,

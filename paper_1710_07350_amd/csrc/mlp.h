@@ -91,7 +91,7 @@ hipError_t launch_fill_u16(uint16_t *p, int64_t n, uint16_t v, hipStream_t st);
 // Section constants (host-computed, passed by value).
 struct SurrDev {
   double C[6], R[36], D[6];
-  double hw[6], inv_hw[6], sw[6];
+  double hw[6], inv_nw[6], sw[6];  // inv_nw = 1/sw: network input scale
   double gx, ax2, bx, gy, ay2, by, eta, etap, bhx, bhy, eh, inv_a, inv_b, lim;
 };
 

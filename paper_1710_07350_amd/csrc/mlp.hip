@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_surr_infer(const MlpDev m, const Sur
     for (int k = 0; k < 6; ++k) z[k] = b.z[k][idx];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      if (k != kMlpSCol) put_input(hh, hl, threadIdx.x, k, static_cast<float>(z[k] * c.inv_hw[k]));
+      if (k != kMlpSCol) put_input(hh, hl, threadIdx.x, k, static_cast<float>(z[k] * c.inv_nw[k]));
   }
   __syncthreads();
   infer_tile<kX2>(m, hh, hl, os);

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const BeamPtrs6 stage, const i
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     float uv = 0.0f, rv = 0.0f;
-    if (q < 6 && q != kMlpSCol) uv = static_cast<float>(zi[q] * c.inv_hw[q]);
+    if (q < 6 && q != kMlpSCol) uv = static_cast<float>(zi[q] * c.inv_nw[q]);
     if (q < kMlpDCol) rv = static_cast<float>(stage.z[q][j] - surr_linear(c, zi, q));
     u[j * 8 + q] = uv;
     r[j * 8 + q] = rv;

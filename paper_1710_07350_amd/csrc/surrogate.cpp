@@ -611,7 +611,6 @@ extern "C" int trk_surrogate_create(const trk_lattice *section, const trk_surrog
   for (int k = 0; k < 6; ++k) {
     c.D[k] = 0.0;
     c.hw[k] = o->half_width[k];
-    c.inv_hw[k] = 1.0 / o->half_width[k];
   }
   c.gx = gx;
   c.ax2 = 2.0 * ax;
@@ -642,6 +641,8 @@ extern "C" int trk_surrogate_create(const trk_lattice *section, const trk_surrog
   sw[5] = dm * pad;
   for (int k = 0; k < 6; ++k) {
     c.sw[k] = std::min(sw[k], o->half_width[k]);
+    // the network sees the admitted set scaled into [-1, 1]
+    c.inv_nw[k] = 1.0 / c.sw[k];
     I.sample_half_width[k] = c.sw[k];
     I.D[k] = 0.0;
   }
