@@ -235,6 +235,19 @@ int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
 int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t workspace_bytes,
                 void *stream);
 
+/* moments without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels, grid and summation order as
+ * trk_moments (bit-identical results), with the partial sums in a static
+ * 256 KiB scratch array of the library (one copy per GPU, held until the
+ * process ends; its device address is looked up on the first call made with
+ * that device current).  Any n_total: the reduction's grid is capped at 1024
+ * blocks, so the scratch never grows; a request that would need more is
+ * refused with TRK_ERANGE.  Nothing is allocated, freed or cleared by the
+ * host.  Every call on one GPU shares that GPU's scratch: calls that may
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; calls in one stream are ordered and safe. */
+int trk_moments_noalloc(const trk_beam *beam, double *out_dev, void *stream);
 
 /* compact_lost (Sec. 2.5): particles in [0, *n_alive) with lost_at >= 0 move
  * behind the survivors, ordered by lost_at descending, ties in their previous

@@ -25,7 +25,7 @@ MAX_BINS = 4096
 # symbols declared in include/trk.h
 EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
            "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_dipole_histogram",
-           "trk_trwake_convolve", "trk_trwake_kick", "trk_moments",
+           "trk_trwake_convolve", "trk_trwake_kick", "trk_moments", "trk_moments_noalloc",
            "trk_compact_lost", "trk_compact_lost_mode", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
            "trk_probe_stream", "trk_probe_fma",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
@@ -128,6 +128,7 @@ def lib():
         L.trk_wake_kick.argtypes = [C.POINTER(BeamStruct), vp, i32, vp, C.POINTER(Wake), d, i32,
                                     vp, sz, vp]
         L.trk_moments.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
+        L.trk_moments_noalloc.argtypes = [C.POINTER(BeamStruct), vp, vp]
         L.trk_compact_lost.argtypes = [C.POINTER(BeamStruct), vp, sz, vp]
         L.trk_compact_lost_mode.argtypes = [C.POINTER(BeamStruct), i32, vp, sz, vp]
         L.trk_elementary.argtypes = [i32, vp, vp, vp, i64, vp]
@@ -388,6 +389,14 @@ def moments(beam: Beam, ws: Workspace, stream=None):
     out = torch.empty(28, dtype=torch.float64, device=beam.z.device)
     _check(lib().trk_moments(C.byref(beam.struct()), out.data_ptr(), ws.ptr, ws.nbytes,
                              _stream_handle(stream)))
+    return out
+
+
+def moments_noalloc(beam: Beam, out, stream=None):
+    """trk_moments_noalloc into the caller's device tensor out[28] (float64):
+    no workspace, the library's static scratch."""
+    _check(lib().trk_moments_noalloc(C.byref(beam.struct()), out.data_ptr(),
+                                     _stream_handle(stream)))
     return out
 
 
