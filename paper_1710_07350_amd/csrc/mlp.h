@@ -13,6 +13,13 @@ constexpr int kMlpInPad = 32;    // K of layer 1; row length of dO and of the W1
 constexpr int kMlpInPadT = 16;   // rows of u^T: 6 inputs, a row of ones, zeros
 constexpr int kMlpOutPad = 16;   // rows of the W4 copy and of dO^T
 constexpr int kMlpHT = 272;      // rows of h^T: 256 activations, a row of ones, zeros
+constexpr int kMlpInK = 16;      // K of layer 1 in inference (6 inputs, zero-padded)
+// inference weight copies (one allocation): W1 [256][16], W2 and W3 [256][256]
+// and W4 [32][256] (6 rows used) with input columns in tile position order
+constexpr int64_t kOffW2i = 256 * kMlpInK;
+constexpr int64_t kOffW3i = kOffW2i + 256 * 256;
+constexpr int64_t kOffW4i = kOffW3i + 256 * 256;
+constexpr int64_t kMlpInferElems = kOffW4i + 32 * 256;
 constexpr int64_t kOffW1 = 0;
 constexpr int64_t kOffB1 = kOffW1 + kMlpHid * kMlpIn;
 constexpr int64_t kOffW2 = kOffB1 + kMlpHid;
@@ -34,6 +41,7 @@ struct MlpDev {
   const uint16_t *w3b;  // [256][256]
   const uint16_t *w2b;  // [256][256]
   const float *b1, *b2, *b3, *b4;
+  uint16_t *wi;         // [kMlpInferElems] inference copies (written per inference call)
 };
 
 struct TrainArgs {

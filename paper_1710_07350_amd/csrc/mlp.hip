@@ -196,119 +196,217 @@ __device__ void mlp_tile(const MlpDev &m, uint16_t *hh, uint16_t *hl, float *os,
 }
 
 // ------------------------------------------------------------------ inference tile
-// Inference evaluates Y^T = W H^T: the weights are the A operand (rows =
-// output features, read from L2 one K step ahead of their use), the tile's
-// activations the B operand.  The accumulator of lane l then holds four
-// consecutive features 4(l/16).. of particle l%16, so the epilogue writes
-// each lane's four new activations with one 8-byte LDS store per half.  The
-// skip path reads the previous activation back as hi + lo (16 significant
-// bits) instead of keeping it in registers, which halves the register
-// footprint and lets two workgroups share a compute unit.
-template <int kX2, int K>
-__device__ __forceinline__ void mma_t(f32x4 (&acc)[4][4], const uint16_t *__restrict__ w, int wstride,
-                                      int f0, const uint16_t *bh, const uint16_t *bl, int bstride) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-  bf16x8 a[4];
+// Inference evaluates Y^T = W H^T on v_mfma_f32_32x32x16_bf16: the weights are
+// the A operand (32 output features x 16 k), the tile's activations the B
+// operand (16 k x 32 particles).  Lane l supplies A row / B column l%32 with
+// the eight k values 8(l/32)..+7, and receives D rows 8i + 4(l/32) + j
+// (i, j = 0..3) of column l%32 in element 4i + j.
+//
+// Activations sit in LDS in that accumulator order: position
+// p = 32b + 16h + 4i + j of a particle's row holds feature 32b + 8i + 4h + j
+// (b the 32-feature block, h the lane half).  A lane's sixteen results of a
+// block are sixteen consecutive positions (two 16-byte stores per half), the
+// next layer reads sixteen consecutive positions per K step, and the input
+// columns of the inference weight copies are permuted to match: the same
+// sum over k in another order.  At a row stride of 264 bf16 (132 dwords) the
+// 16-byte stores and loads of a lane group fall on distinct banks.
+//
+// Work split: a workgroup of four waves owns 64 particles; wave w computes
+// features [64w, 64w + 64) of each hidden layer for all of them (2 x 2
+// accumulator blocks).  The skip path keeps each lane's previous activations
+// in FP32 registers, as the training forward does; the output layer splits
+// K between wave pairs and adds the two halves in a fixed order.  Two
+// workgroups share a compute unit (78 KB of LDS each), so the matrix cores of
+// one overlap the SiLU epilogue of the other.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kULds2 = kMlpInK + 8;  // input-tile row stride (bf16)
+
+__device__ __forceinline__ f32x16 mma32(f32x16 c, bf16x8 a, bf16x8 b) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc[mt][nt] = W(rows f0 + 32mt .., KS*16 k) x H^T(KS*16 k, particles 32nt ..).
+// Software pipelined: the weight fragments (from L2) are loaded three K steps
+// ahead and the activation fragments (from LDS) one step ahead, so a step's
+// matrix products wait only for data requested two to three steps earlier.
+// The first step starts from a zero accumulator operand.
+template <int kX2, int KS>
+__device__ __forceinline__ void kloop32(f32x16 (&acc)[2][2], const uint16_t *__restrict__ w,
+                                        int wstride, int f0, const uint16_t *bh,
+                                        const uint16_t *bl, int bstride) {
+  constexpr int kA = KS < 3 ? KS : 3;  // weight steps in flight
+  const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
+  const uint16_t *wr0 = w + static_cast<size_t>(f0 + r) * wstride + 8 * h;
+  const uint16_t *wr1 = wr0 + static_cast<size_t>(32) * wstride;
+  const uint16_t *b0 = bh + r * bstride + 8 * h, *b1 = b0 + 32 * bstride;
+  const uint16_t *c0 = bl + r * bstride + 8 * h, *c1 = c0 + 32 * bstride;
+  bf16x8 a[kA][2], x[2][2], y[2][2];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) a[mt] = ld8(w + static_cast<size_t>(f0 + 16 * mt + r) * wstride + 8 * g);
-#pragma unroll 1
-  for (int kk = 0; kk < K / 32; ++kk) {
-    bf16x8 an[4];
-    if (kk + 1 < K / 32) {
+  for (int q = 0; q < kA; ++q) {
+    a[q][0] = ld8(wr0 + 16 * q);
+    a[q][1] = ld8(wr1 + 16 * q);
+  }
+  x[0][0] = ld8(b0);
+  x[0][1] = ld8(b1);
+  if constexpr (kX2) {
+    y[0][0] = ld8(c0);
+    y[0][1] = ld8(c1);
+  }
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        an[mt] = ld8(w + static_cast<size_t>(f0 + 16 * mt + r) * wstride + 32 * (kk + 1) + 8 * g);
-    }
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const bf16x8 b = ld8(bh + (16 * nt + r) * bstride + 32 * kk + 8 * g);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(acc[mt][nt], a[mt], b);
+  for (int s = 0; s < KS; ++s) {
+    const int cur = s & 1, nxt = cur ^ 1, sa = s % kA;
+    // the fences keep the compiler from sinking the early loads next to
+    // their use (it does, to save registers, and the wave then stalls on
+    // the L2 latency every step)
+    __builtin_amdgcn_sched_barrier(0);
+    if (s + 1 < KS) {
+      x[nxt][0] = ld8(b0 + 16 * (s + 1));
+      x[nxt][1] = ld8(b1 + 16 * (s + 1));
       if constexpr (kX2) {
-        const bf16x8 b2 = ld8(bl + (16 * nt + r) * bstride + 32 * kk + 8 * g);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[mt][nt] = mma(acc[mt][nt], a[mt], b2);
+        y[nxt][0] = ld8(c0 + 16 * (s + 1));
+        y[nxt][1] = ld8(c1 + 16 * (s + 1));
       }
     }
-    if (kk + 1 < K / 32) {
+    __builtin_amdgcn_sched_barrier(0);
+    const f32x16 z = {};
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        acc[mt][nt] = mma32(s == 0 ? z : acc[mt][nt], a[sa][mt], x[cur][nt]);
+    if constexpr (kX2) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mma32(acc[mt][nt], a[sa][mt], y[cur][nt]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (s + kA < KS) {
+      a[sa][0] = ld8(wr0 + 16 * (s + kA));
+      a[sa][1] = ld8(wr1 + 16 * (s + kA));
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// bias, SiLU, skip (kFirst: none), the new activations as hi (and lo) bf16
+// into the tile at their positions; prev keeps them in FP32
+template <int kX2, bool kFirst>
+__device__ __forceinline__ void epi32(const f32x16 (&acc)[2][2], f32x16 (&prev)[2][2],
+                                      const float *__restrict__ bias, uint16_t *hh, uint16_t *hl,
+                                      int f0) {
+  const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    float bb[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 q = *reinterpret_cast<const float4 *>(bias + f0 + 32 * mt + 8 * i + 4 * h);
+      bb[4 * i] = q.x;
+      bb[4 * i + 1] = q.y;
+      bb[4 * i + 2] = q.z;
+      bb[4 * i + 3] = q.w;
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      float v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float s = silu(acc[mt][nt][q] + bb[q]);
+        v[q] = kFirst ? s : prev[mt][nt][q] + s;
+        prev[mt][nt][q] = v[q];
+      }
+      uint32_t ph[8], pl[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        ph[t] = pack_bf16(v[2 * t], v[2 * t + 1]);
+        if constexpr (kX2) pl[t] = pack_bf16(v[2 * t] - lo_half(ph[t]), v[2 * t + 1] - hi_half(ph[t]));
+      }
+      const int o = (32 * nt + r) * kLds + f0 + 32 * mt + 16 * h;
+      *reinterpret_cast<uint4 *>(hh + o) = uint4{ph[0], ph[1], ph[2], ph[3]};
+      *reinterpret_cast<uint4 *>(hh + o + 8) = uint4{ph[4], ph[5], ph[6], ph[7]};
+      if constexpr (kX2) {
+        *reinterpret_cast<uint4 *>(hl + o) = uint4{pl[0], pl[1], pl[2], pl[3]};
+        *reinterpret_cast<uint4 *>(hl + o + 8) = uint4{pl[4], pl[5], pl[6], pl[7]};
+      }
     }
   }
 }
 
-template <bool kFirst>
-__device__ __forceinline__ void epi_t(const f32x4 (&acc)[4][4], const float *__restrict__ bias,
-                                      uint16_t *hh, uint16_t *hl, int f0) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+// LDS of one inference workgroup
+struct InferLds {
+  uint16_t hh[kRows * kLds];
+  uint16_t hl[kRows * kLds];
+  uint16_t uh[kRows * kULds2];
+  uint16_t ul[kRows * kULds2];
+  float op[2][kRows * 8];  // output-layer K halves
+};
+
+// thread t < 64: particle t's normalised inputs (s ignored) as hi/lo bf16
+__device__ __forceinline__ void put_row(InferLds &L, int t, const float (&u)[kMlpIn]) {
+  uint32_t ph[8] = {}, pl[8] = {};
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    const int f = f0 + 16 * mt + 4 * g;
-    float bb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bb[q] = bias[f + q];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int o = (16 * nt + r) * kLds + f;
-      float v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = silu(acc[mt][nt][q] + bb[q]);
-      if constexpr (!kFirst) {
-        const uint2 oh = *reinterpret_cast<const uint2 *>(hh + o);
-        const uint2 ol = *reinterpret_cast<const uint2 *>(hl + o);
-        v[0] = (lo_half(oh.x) + lo_half(ol.x)) + v[0];
-        v[1] = (hi_half(oh.x) + hi_half(ol.x)) + v[1];
-        v[2] = (lo_half(oh.y) + lo_half(ol.y)) + v[2];
-        v[3] = (hi_half(oh.y) + hi_half(ol.y)) + v[3];
-      }
-      uint2 ph, pl;
-      ph.x = pack_bf16(v[0], v[1]);
-      ph.y = pack_bf16(v[2], v[3]);
-      pl.x = pack_bf16(v[0] - lo_half(ph.x), v[1] - hi_half(ph.x));
-      pl.y = pack_bf16(v[2] - lo_half(ph.y), v[3] - hi_half(ph.y));
-      *reinterpret_cast<uint2 *>(hh + o) = ph;
-      *reinterpret_cast<uint2 *>(hl + o) = pl;
-    }
+  for (int k = 0; k < kMlpIn; k += 2) {
+    const float a = k == kMlpSCol ? 0.0f : u[k];
+    const float b = k + 1 == kMlpSCol ? 0.0f : u[k + 1];
+    ph[k / 2] = pack_bf16(a, b);
+    pl[k / 2] = pack_bf16(a - lo_half(ph[k / 2]), b - hi_half(ph[k / 2]));
   }
+  uint16_t *uh = L.uh + t * kULds2, *ul = L.ul + t * kULds2;
+  *reinterpret_cast<uint4 *>(uh) = uint4{ph[0], ph[1], ph[2], ph[3]};
+  *reinterpret_cast<uint4 *>(uh + 8) = uint4{ph[4], ph[5], ph[6], ph[7]};
+  *reinterpret_cast<uint4 *>(ul) = uint4{pl[0], pl[1], pl[2], pl[3]};
+  *reinterpret_cast<uint4 *>(ul + 8) = uint4{pl[4], pl[5], pl[6], pl[7]};
 }
 
-// The network for one 64-particle tile whose inputs are in LDS (uh/ul,
-// aliased with hh/hl); leaves o[row][0..8) in os (columns >= 6 zero).
+// The network for the 64 particles whose inputs are in L.uh/L.ul; thread
+// t < 64 reads output k of particle t as out(L, t, k) afterwards.
 template <int kX2>
-__device__ void infer_tile(const MlpDev &m, uint16_t *hh, uint16_t *hl, float *os) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4, w = threadIdx.x >> 6, f0 = 64 * w;
-  f32x4 acc[4][4];
-  zero(acc);
-  mma_t<kX2, kMlpInPad>(acc, m.w1f, kMlpInPad, f0, hh, hl, kULds);
+__device__ void infer_tile32(const MlpDev &m, InferLds &L) {
+  const int l = threadIdx.x & 63, r = l & 31, h = l >> 5, w = threadIdx.x >> 6, f0 = 64 * w;
+  const uint16_t *wi = m.wi;
+  f32x16 acc[2][2], prev[2][2];
+  kloop32<kX2, kMlpInK / 16>(acc, wi, kMlpInK, f0, L.uh, L.ul, kULds2);
+  epi32<kX2, true>(acc, prev, m.b1, L.hh, L.hl, f0);
   __syncthreads();
-  epi_t<true>(acc, m.b1, hh, hl, f0);
+  kloop32<kX2, kMlpHid / 16>(acc, wi + kOffW2i, kMlpHid, f0, L.hh, L.hl, kLds);
+  __syncthreads();  // every wave has read h1 before it is overwritten
+  epi32<kX2, false>(acc, prev, m.b2, L.hh, L.hl, f0);
   __syncthreads();
-  zero(acc);
-  mma_t<kX2, kMlpHid>(acc, m.w2f, kMlpHid, f0, hh, hl, kLds);
+  kloop32<kX2, kMlpHid / 16>(acc, wi + kOffW3i, kMlpHid, f0, L.hh, L.hl, kLds);
   __syncthreads();
-  epi_t<false>(acc, m.b2, hh, hl, f0);
+  epi32<kX2, false>(acc, prev, m.b3, L.hh, L.hl, f0);
   __syncthreads();
-  zero(acc);
-  mma_t<kX2, kMlpHid>(acc, m.w3f, kMlpHid, f0, hh, hl, kLds);
-  __syncthreads();
-  epi_t<false>(acc, m.b3, hh, hl, f0);
-  __syncthreads();
-  // output layer: 16 output rows (6 used) x particles 16w..16w+15
-  f32x4 o{0.f, 0.f, 0.f, 0.f};
+  // output layer: wave w takes particles 32(w&1).. and K steps 8(w>>1)..+7
+  {
+    const int nt = w & 1, kh = w >> 1;
+    const uint16_t *wa = wi + kOffW4i + r * kMlpHid + 8 * h + 128 * kh;
+    const uint16_t *xb = L.hh + (32 * nt + r) * kLds + 8 * h + 128 * kh;
+    const uint16_t *xl = L.hl + (32 * nt + r) * kLds + 8 * h + 128 * kh;
+    f32x16 o = {};
 #pragma unroll 2
-  for (int kk = 0; kk < kMlpHid / 32; ++kk) {
-    const bf16x8 a = ld8(m.w4f + r * kMlpHid + 32 * kk + 8 * g);
-    o = mma(o, a, ld8(hh + (16 * w + r) * kLds + 32 * kk + 8 * g));
-    if constexpr (kX2) o = mma(o, a, ld8(hl + (16 * w + r) * kLds + 32 * kk + 8 * g));
-  }
-  if (g < 2) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int out = 4 * g + q;
-      os[(16 * w + r) * 8 + out] = out < kMlpOut ? o[q] + m.b4[out] : 0.0f;
+    for (int s = 0; s < 8; ++s) {
+      const bf16x8 a = ld8(wa + 16 * s);
+      o = mma32(o, a, ld8(xb + 16 * s));
+      if constexpr (kX2) o = mma32(o, a, ld8(xl + 16 * s));
+    }
+    // element j (i = 0) holds output 4h + j of particle 32nt + r
+    float *op = L.op[kh] + (32 * nt + r) * 8 + 4 * h;
+    if (h == 0) {
+      op[0] = o[0];
+      op[1] = o[1];
+      op[2] = o[2];
+      op[3] = o[3];
+    } else {
+      op[0] = o[0];
+      op[1] = o[1];
     }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ float out_of(const MlpDev &m, const InferLds &L, int t, int k) {
+  return (L.op[0][t * 8 + k] + L.op[1][t * 8 + k]) + m.b4[k];
 }
 
 // input tile: 64 rows x 32 (6 used, s column zero) as hi/lo bf16
@@ -327,62 +425,85 @@ __device__ __forceinline__ void clear_input(uint16_t *uh, uint16_t *ul) {
 
 }  // namespace
 
+// Inference copies of the bfloat16 forward weights: W1 with K = 16, and W2,
+// W3, W4 (32 rows, 6 used) with their input columns in the tile's position
+// order (position p holds feature 32b + 8i + 4h + j for p = 32b + 16h + 4i + j).
+__global__ __launch_bounds__(kBlock) void k_mlp_infer_copy(const MlpDev m) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= kMlpInferElems) return;
+  uint16_t v;
+  if (i < kOffW2i) {
+    v = m.w1f[(i / kMlpInK) * kMlpInPad + i % kMlpInK];
+  } else {
+    const int64_t j = i < kOffW3i ? i - kOffW2i : (i < kOffW4i ? i - kOffW3i : i - kOffW4i);
+    const int row = static_cast<int>(j >> 8), p = static_cast<int>(j & 255);
+    const int f = 32 * (p >> 5) + 8 * ((p >> 2) & 3) + 4 * ((p >> 4) & 1) + (p & 3);
+    if (i < kOffW3i)
+      v = m.w2f[row * kMlpHid + f];
+    else if (i < kOffW4i)
+      v = m.w3f[row * kMlpHid + f];
+    else
+      v = row < kMlpOut ? m.w4f[row * kMlpHid + f] : uint16_t{0};
+  }
+  m.wi[i] = v;
+}
+
 // ------------------------------------------------------------------ forward
 // o = MLP(u) for rows of u[n][8] (columns 0..5; column 4 ignored) -> out[n][8]
 template <int kX2>
-__global__ __launch_bounds__(kBlock) void k_mlp_forward(const MlpDev m, const float *__restrict__ u,
-                                                        int64_t n, float *__restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint16_t hh[kRows * kLds];
-  __shared__ __attribute__((aligned(16))) uint16_t hl[kRows * kLds];
-  __shared__ float os[kRows * 8];
+__global__ __launch_bounds__(kBlock, 2) void k_mlp_forward(const MlpDev m, const float *__restrict__ u,
+                                                           int64_t n, float *__restrict__ out) {
+  __shared__ __attribute__((aligned(16))) InferLds L;
   const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows;
-  clear_input(hh, hl);
-  __syncthreads();
-  for (int i = threadIdx.x; i < kRows * kMlpIn; i += kBlock) {
-    const int row = i / kMlpIn, k = i % kMlpIn;
-    if (row0 + row < n && k != kMlpSCol) put_input(hh, hl, row, k, u[(row0 + row) * 8 + k]);
+  const int t = threadIdx.x;
+  if (t < kRows) {
+    float uu[kMlpIn] = {};
+    if (row0 + t < n)
+#pragma unroll
+      for (int k = 0; k < kMlpIn; ++k) uu[k] = u[(row0 + t) * 8 + k];
+    put_row(L, t, uu);
   }
   __syncthreads();
-  infer_tile<kX2>(m, hh, hl, os);
-  for (int i = threadIdx.x; i < kRows * 8; i += kBlock) {
-    const int row = i / 8;
-    if (row0 + row < n) out[row0 * 8 + i] = os[i];
+  infer_tile32<kX2>(m, L);
+  if (t < kRows && row0 + t < n) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[(row0 + t) * 8 + k] = k < kMlpOut ? out_of(m, L, t, k) : 0.0f;
   }
 }
-
 
 // ------------------------------------------------------------------ surrogate
 // y = C + R z + D o(N(z)) for the admitted particles adm[0 .. *n_adm), in
 // place (x, x', y, y', s; delta unchanged).  Thread t < 64 of a workgroup
 // holds particle t of the tile in FP64 from its load to its store.
 template <int kX2>
-__global__ __launch_bounds__(kBlock) void k_surr_infer(const MlpDev m, const SurrDev c, const BeamPtrs6 b,
-                                                       const uint32_t *__restrict__ adm,
-                                                       const int64_t *__restrict__ n_adm) {
-  __shared__ __attribute__((aligned(16))) uint16_t hh[kRows * kLds];
-  __shared__ __attribute__((aligned(16))) uint16_t hl[kRows * kLds];
-  __shared__ float os[kRows * 8];
+__global__ __launch_bounds__(kBlock, 2) void k_surr_infer(const MlpDev m, const SurrDev c,
+                                                          const BeamPtrs6 b,
+                                                          const uint32_t *__restrict__ adm,
+                                                          const int64_t *__restrict__ n_adm) {
+  __shared__ __attribute__((aligned(16))) InferLds L;
   const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows;
   const int64_t na = *n_adm;
   if (row0 >= na) return;  // whole workgroup
-  clear_input(hh, hl);
-  __syncthreads();
+  const int t = threadIdx.x;
   double z[6];
   int64_t idx = -1;
-  if (threadIdx.x < kRows && row0 + threadIdx.x < na) {
-    idx = adm[row0 + threadIdx.x];
+  if (t < kRows) {
+    float uu[kMlpIn] = {};
+    if (row0 + t < na) {
+      idx = adm[row0 + t];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) z[k] = b.z[k][idx];
+      for (int k = 0; k < 6; ++k) z[k] = b.z[k][idx];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-      if (k != kMlpSCol) put_input(hh, hl, threadIdx.x, k, static_cast<float>(z[k] * c.inv_nw[k]));
+      for (int k = 0; k < kMlpIn; ++k) uu[k] = static_cast<float>(z[k] * c.inv_nw[k]);
+    }
+    put_row(L, t, uu);
   }
   __syncthreads();
-  infer_tile<kX2>(m, hh, hl, os);
+  infer_tile32<kX2>(m, L);
   if (idx >= 0) {
 #pragma unroll
     for (int i = 0; i < kMlpDCol; ++i)
-      b.z[i][idx] = surr_linear(c, z, i) + c.D[i] * static_cast<double>(os[threadIdx.x * 8 + i]);
+      b.z[i][idx] = surr_linear(c, z, i) + c.D[i] * static_cast<double>(out_of(m, L, t, i));
   }
 }
 
@@ -590,10 +711,18 @@ __global__ void k_fill_u16(uint16_t *p, int64_t n, uint16_t v) {
 }
 
 // ------------------------------------------------------------------ launchers
+// the inference copies follow the forward copies the last Adam step wrote
+hipError_t launch_infer_copy(const MlpDev &m, hipStream_t st) {
+  const int grid = static_cast<int>((kMlpInferElems + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_mlp_infer_copy, dim3(grid), dim3(kBlock), 0, st, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_mlp_forward(const MlpDev &m, const float *u, int64_t n, float *out, int x2,
                               hipStream_t st) {
   const int64_t grid = (n + kRows - 1) / kRows;
   if (grid == 0) return hipSuccess;
+  if (hipError_t e = launch_infer_copy(m, st); e != hipSuccess) return e;
   if (x2)
     hipLaunchKernelGGL(k_mlp_forward<1>, dim3(grid), dim3(kBlock), 0, st, m, u, n, out);
   else
@@ -606,6 +735,7 @@ hipError_t launch_surr_infer(const MlpDev &m, const SurrDev &c, const BeamPtrs6 
                              hipStream_t st) {
   const int64_t grid = (n_total + kRows - 1) / kRows;
   if (grid == 0) return hipSuccess;
+  if (hipError_t e = launch_infer_copy(m, st); e != hipSuccess) return e;
   if (x2)
     TRK_LAUNCH((k_surr_infer<1>), dim3(grid), dim3(kBlock), 0, st, m, c, b, adm, n_adm);
   else

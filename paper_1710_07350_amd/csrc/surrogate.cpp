@@ -50,6 +50,7 @@ int check_prec(int32_t p) {
 struct trk_mlp {
   float *w = nullptr, *m = nullptr, *v = nullptr;  // [NPARAM] each, one allocation
   uint16_t *bf = nullptr;                          // bf16 copies, one allocation
+  uint16_t *wi = nullptr;                          // inference copies
   uint16_t *w1f, *w2f, *w3f, *w4f, *w4b, *w3b, *w2b;
   int64_t step = 0;
   double p1 = 1.0, p2 = 1.0;  // beta1^step, beta2^step (products in step order)
@@ -70,6 +71,7 @@ MlpDev dev_of(const trk_mlp *m) {
   d.b2 = m->w + kOffB2;
   d.b3 = m->w + kOffB3;
   d.b4 = m->w + kOffB4;
+  d.wi = m->wi;
   return d;
 }
 
@@ -209,8 +211,10 @@ extern "C" int trk_mlp_create(const float *params_host, trk_mlp **out) {
   if (m == nullptr) return fail(TRK_ENOMEM, "host allocation");
   hipError_t e = hipMalloc(&m->w, 3 * kMlpNParam * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&m->bf, (kWfElems + kWbElems) * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMalloc(&m->wi, kMlpInferElems * sizeof(uint16_t));
   if (e != hipSuccess) {
     (void)hipFree(m->w);
+    (void)hipFree(m->bf);
     delete m;
     return fail(TRK_ENOMEM, std::string("network allocation: ") + hipGetErrorString(e));
   }
@@ -233,6 +237,7 @@ extern "C" int trk_mlp_create(const float *params_host, trk_mlp **out) {
   if (e != hipSuccess) {
     (void)hipFree(m->w);
     (void)hipFree(m->bf);
+    (void)hipFree(m->wi);
     delete m;
     return hip_fail(e, "network upload");
   }
@@ -244,6 +249,7 @@ extern "C" void trk_mlp_destroy(trk_mlp *m) {
   if (m == nullptr) return;
   (void)hipFree(m->w);
   (void)hipFree(m->bf);
+  (void)hipFree(m->wi);
   delete m;
 }
 
