@@ -700,8 +700,10 @@ def sweep_bench(args):
 def ablation_bench(args):
     """Moment reductions (Sec. 2.4): the ring at 1e6 particles, 32 turns, one
     turn per launch, with no moments, with the per-turn moments fused into
-    the run kernel (shifted one-pass rows), and with a separate two-pass
-    moments call after every turn."""
+    the run kernel (shifted one-pass rows), with a separate two-pass
+    moments call after every turn, and with the separate call on
+    Kahan-compensated sums (the paper's optional compensated reductions).
+    Also the cost of one standalone call of each on the 1e6-particle beam."""
     import torch
     from paper_1710_07350_amd import binding as B
     from paper_1710_07350_amd import inputs
@@ -718,10 +720,11 @@ def ablation_bench(args):
         a = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
         a.record()
-        if mode == "separate":
+        if mode in ("separate", "compensated"):
+            f = B.moments if mode == "separate" else B.moments_compensated
             for t in range(turns):
                 B.track(b, L, 1, ws, seed=7, first_pass=t)
-                mom[t].copy_(B.moments(b, ws))
+                mom[t].copy_(f(b, ws))
         else:
             B.track(b, L, turns, ws, seed=7, passes_per_launch=1,
                     moments=mom if mode == "fused" else None)
@@ -730,15 +733,32 @@ def ablation_bench(args):
         return a.elapsed_time(e)
 
     out = {}
-    for mode in ("none", "fused", "separate", "none", "fused", "separate"):
+    modes = ("none", "fused", "separate", "compensated")
+    for mode in modes:  # warm-up (first launches, allocations)
+        run(mode)
+    for mode in modes * 3:
         out.setdefault(mode, []).append(run(mode))
     res = {m: float(np.median(v)) / turns for m, v in out.items()}
+
+    def one_call(f):
+        ts = []
+        for _ in range(11):
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record()
+            f(src, ws)
+            e.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(e))
+        return float(np.median(ts[1:]))
     return {"metric": "ms per ring turn (1e6 particles) by moment-reduction scheme", "unit": "ms",
             "config": {"workload": f"storage ring, {n:.0e} particles, {turns} turns, one turn "
                                    "per launch"},
             "ms_per_turn": res,
-            "moment_cost_ms_per_turn": {"fused": res["fused"] - res["none"],
-                                        "separate": res["separate"] - res["none"]}}
+            "moment_cost_ms_per_turn": {k: res[k] - res["none"]
+                                        for k in ("fused", "separate", "compensated")},
+            "standalone_call_ms": {"plain": one_call(B.moments),
+                                   "compensated": one_call(B.moments_compensated)}}
 
 
 def ceilings_bench(args):

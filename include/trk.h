@@ -235,6 +235,17 @@ int trk_trwake_kick(trk_beam *beam, const int64_t *dipole_dev, int32_t nbins,
 int trk_moments(const trk_beam *beam, double *out_dev, void *workspace, size_t workspace_bytes,
                 void *stream);
 
+/* moments with compensated sums (the optional Kahan reductions of
+ * Sec. 2.4): as trk_moments, but every sum is carried as a pair (s, c):
+ * each thread adds its particles by Neumaier's variant of Kahan summation,
+ * pairs are combined by TwoSum (the exact rounding error of each addition
+ * kept), the value is s + c.  The means come from the first pass, the
+ * central moments from sums of (z - mean) products.  Deterministic for a
+ * given n_total; means within two units in the last place of exactly
+ * rounded sums.  Same workspace as trk_moments. */
+int trk_moments_compensated(const trk_beam *beam, double *out_dev, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
 /* moments without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): the same kernels, grid and summation order as

@@ -25,7 +25,7 @@ MAX_BINS = 4096
 # symbols declared in include/trk.h
 EXPORTS = ("trk_lattice_create", "trk_lattice_destroy", "trk_workspace_size", "trk_track",
            "trk_histogram", "trk_wake_convolve", "trk_wake_kick", "trk_dipole_histogram",
-           "trk_trwake_convolve", "trk_trwake_kick", "trk_moments", "trk_moments_noalloc",
+           "trk_trwake_convolve", "trk_trwake_kick", "trk_moments", "trk_moments_noalloc", "trk_moments_compensated",
            "trk_compact_lost", "trk_compact_lost_mode", "trk_elementary", "trk_philox4x32_10", "trk_gauss",
            "trk_probe_stream", "trk_probe_fma",
            "trk_status_string", "trk_last_error", "trk_profile_enable", "trk_profile_read",
@@ -129,6 +129,7 @@ def lib():
                                     vp, sz, vp]
         L.trk_moments.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
         L.trk_moments_noalloc.argtypes = [C.POINTER(BeamStruct), vp, vp]
+        L.trk_moments_compensated.argtypes = [C.POINTER(BeamStruct), vp, vp, sz, vp]
         L.trk_compact_lost.argtypes = [C.POINTER(BeamStruct), vp, sz, vp]
         L.trk_compact_lost_mode.argtypes = [C.POINTER(BeamStruct), i32, vp, sz, vp]
         L.trk_elementary.argtypes = [i32, vp, vp, vp, i64, vp]
@@ -389,6 +390,15 @@ def moments(beam: Beam, ws: Workspace, stream=None):
     out = torch.empty(28, dtype=torch.float64, device=beam.z.device)
     _check(lib().trk_moments(C.byref(beam.struct()), out.data_ptr(), ws.ptr, ws.nbytes,
                              _stream_handle(stream)))
+    return out
+
+
+def moments_compensated(beam: Beam, ws: Workspace, stream=None):
+    """trk_moments_compensated: the moments with Kahan-compensated sums."""
+    import torch
+    out = torch.empty(28, dtype=torch.float64, device=beam.z.device)
+    _check(lib().trk_moments_compensated(C.byref(beam.struct()), out.data_ptr(), ws.ptr,
+                                         ws.nbytes, _stream_handle(stream)))
     return out
 
 

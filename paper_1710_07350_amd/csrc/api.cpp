@@ -1107,6 +1107,27 @@ extern "C" int trk_moments(const trk_beam *beam, double *out_dev, void *workspac
   return TRK_OK;
 }
 
+extern "C" int trk_moments_compensated(const trk_beam *beam, double *out_dev, void *workspace,
+                                       size_t workspace_bytes_, void *stream) {
+  if (int r = check_beam(beam)) return r;
+  if (int r = check_dev(out_dev, "out")) return r;
+  if (int r = check_ws(workspace, workspace_bytes_, beam->n_total)) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w = carve_workspace(workspace, beam->n_total);
+  double *z[6];
+  beam_ptrs(beam, z);
+  const int g = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nblocks(beam->n_total), 1024)));
+  HIP_TRY(launch_mom_partial_c(z, beam->n_alive, beam->n_total, nullptr, w.mom_part, g, st),
+          "compensated moments");
+  HIP_TRY(launch_mom_finalize_c(w.mom_part, g, nullptr, w.mom_tmp, w.mom_shift, st),
+          "compensated moments");
+  HIP_TRY(launch_mom_partial_c(z, beam->n_alive, beam->n_total, w.mom_shift, w.mom_part, g, st),
+          "compensated moments");
+  HIP_TRY(launch_mom_finalize_c(w.mom_part, g, w.mom_shift, out_dev, nullptr, st),
+          "compensated moments");
+  return TRK_OK;
+}
+
 extern "C" int trk_compact_lost_mode(trk_beam *beam, int32_t mode, void *workspace,
                                      size_t workspace_bytes_, void *stream) {
   if (mode != TRK_COMPACT_STABLE && mode != TRK_COMPACT_SWAP && mode != TRK_COMPACT_SORT)

@@ -516,6 +516,141 @@ hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const d
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ compensated moments
+// The optional compensated reductions of Sec. 2.4: every sum is carried as
+// an unevaluated pair (s, c).  A thread adds its particles with Neumaier's
+// variant of Kahan summation; pairs are combined with TwoSum (the exact
+// rounding error of s1 + s2 goes into c) in the fixed order of the plain
+// reductions; the value of a sum is s + c.
+__device__ __forceinline__ void neu_add(double &s, double &c, double x) {
+  const double t = s + x;
+  c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+__device__ __forceinline__ void pair_add(double &s, double &c, double s2, double c2) {
+  const double t = s + s2;
+  const double bp = t - s;
+  const double e = (s - (t - bp)) + (s2 - bp);
+  s = t;
+  c = (c + c2) + e;
+}
+
+// pairs of one block summed: wave butterfly, then the waves in order;
+// row[0..28) = s, row[28..56) = c
+__device__ __forceinline__ void block_pair_row(double (&s)[28], double (&c)[28], double *row) {
+  __shared__ double ps[kWaves][28], pc[kWaves][28];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 28; ++k) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const double s2 = __shfl_xor(s[k], m, 64), c2 = __shfl_xor(c[k], m, 64);
+      pair_add(s[k], c[k], s2, c2);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 28; ++k) {
+      ps[wave][k] = s[k];
+      pc[wave][k] = c[k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 28) {
+    double a = ps[0][threadIdx.x], b = pc[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) pair_add(a, b, ps[w][threadIdx.x], pc[w][threadIdx.x]);
+    row[threadIdx.x] = a;
+    row[28 + threadIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mom_partial_c(Z6 z, const int64_t *__restrict__ n_alive,
+                                                          int64_t n_total,
+                                                          const double *__restrict__ shift,
+                                                          double *__restrict__ part) {
+  const int64_t n = min(*n_alive, n_total);
+  double cs[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) cs[k] = shift ? shift[k] : 0.0;
+  double s[28], c[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) s[k] = c[k] = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double d[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d[k] = z.p[k][i] - cs[k];
+    s[0] += 1.0;  // counts stay exact integers
+#pragma unroll
+    for (int k = 0; k < 6; ++k) neu_add(s[1 + k], c[1 + k], d[k]);
+    int o = 7;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = k; l < 6; ++l, ++o) neu_add(s[o], c[o], d[k] * d[l]);
+  }
+  block_pair_row(s, c, part + static_cast<int64_t>(blockIdx.x) * 56);
+}
+
+// sum of the nrows rows of pairs in a fixed order; then as k_mom_finalize
+__global__ __launch_bounds__(kBlock) void k_mom_finalize_c(const double *__restrict__ part, int nrows,
+                                                           const double *__restrict__ shift,
+                                                           double *__restrict__ out,
+                                                           double *__restrict__ mean_out) {
+  double s[28], c[28];
+#pragma unroll
+  for (int k = 0; k < 28; ++k) s[k] = c[k] = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 28; ++k)
+      pair_add(s[k], c[k], part[static_cast<int64_t>(r) * 56 + k],
+               part[static_cast<int64_t>(r) * 56 + 28 + k]);
+  }
+  __shared__ double tot[56];
+  block_pair_row(s, c, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v[28];
+    for (int k = 0; k < 28; ++k) v[k] = tot[k] + tot[28 + k];
+    const double n = v[0];
+    if (n == 0.0) {
+      for (int k = 0; k < 28; ++k) out[k] = 0.0;
+      if (mean_out)
+        for (int k = 0; k < 6; ++k) mean_out[k] = 0.0;
+      return;
+    }
+    double m[6];
+    for (int k = 0; k < 6; ++k) m[k] = v[1 + k] / n;
+    out[0] = n;
+    // the compensated first pass already gives the means to about an ulp;
+    // the second pass (sums of z - mean) only centres the second moments
+    for (int k = 0; k < 6; ++k) {
+      out[1 + k] = shift ? shift[k] : m[k];
+      if (mean_out) mean_out[k] = m[k];
+    }
+    int idx = 7;
+    for (int k = 0; k < 6; ++k)
+      for (int l = k; l < 6; ++l, ++idx) out[idx] = v[idx] / n - m[k] * m[l];
+  }
+}
+
+hipError_t launch_mom_partial_c(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                                const double *shift, double *part, int grid, hipStream_t st) {
+  Z6 zz;
+  for (int k = 0; k < 6; ++k) zz.p[k] = z[k];
+  hipLaunchKernelGGL(k_mom_partial_c, dim3(grid), dim3(kBlock), 0, st, zz, n_alive, n_total, shift,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_mom_finalize_c(const double *part, int nrows, const double *shift, double *out,
+                                 double *mean_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mom_finalize_c, dim3(1), dim3(kBlock), 0, st, part, nrows, shift, out,
+                     mean_out);
+  return hipGetLastError();
+}
+
 __global__ void k_zero_u32(uint32_t *p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }

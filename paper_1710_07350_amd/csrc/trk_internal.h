@@ -220,6 +220,11 @@ hipError_t launch_mom_partial(double *const z[6], const int64_t *n_alive, int64_
                               const double *shift, double *part, int grid, hipStream_t st);
 hipError_t launch_mom_finalize(const double *part, int nrows, int npass, const double *shift,
                                double *out, int out_stride, double *mean_out, hipStream_t st);
+// compensated two-pass moments: rows of 56 (28 sums, 28 compensations)
+hipError_t launch_mom_partial_c(double *const z[6], const int64_t *n_alive, int64_t n_total,
+                                const double *shift, double *part, int grid, hipStream_t st);
+hipError_t launch_mom_finalize_c(const double *part, int nrows, const double *shift, double *out,
+                                 double *mean_out, hipStream_t st);
 hipError_t launch_compact(double *const z[6], uint32_t *id, int64_t *lost_at, int64_t *n_alive,
                           int64_t n_total, const Workspace &w, hipStream_t st);
 // the paper's sparse swap (TRK_COMPACT_SWAP) or sort by key (TRK_COMPACT_SORT)

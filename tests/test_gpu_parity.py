@@ -385,6 +385,32 @@ def test_moments_call(torch):
             moments_close(g, r, rtol=1e-13)
 
 
+def test_compensated_moments_call(torch):
+    """trk_moments_compensated (Kahan-compensated sums, Sec. 2.4) against the
+    oracle's compensated two-pass moments: means within 2 ulp, central
+    moments within 1e-15 of sigma_k sigma_l; the plain call stays within its
+    1e-13 of the beam scale.
+    An offset beam with a lost tail exercises n_alive and the shift."""
+    for n in (1, 2, 1000, 300_001, 4_000_000):
+        d = inputs.gaussian_beam(n, seed=n + 7)
+        d["z"] += np.array([[1e-2], [1e-5], [-2e-3], [0], [1.5], [1e-3]])
+        beam = B.Beam.from_inputs(d)
+        if n > 1000:
+            beam.n_alive.fill_(n - n // 9)
+        ws = B.Workspace(beam.n)
+        g = B.moments_compensated(beam, ws).cpu().numpy()
+        h = beam.host()
+        ob = oracle.Beam(h["z"], h["id"], np.where(np.arange(n) < h["n_alive"], -1, 5).astype(np.int64))
+        r = oracle.moments(ob)
+        if n == 1:
+            assert g[0] == 1 and np.array_equal(g[1:7], r[1:7]) and not g[7:].any()
+            continue
+        assert g[0] == r[0]
+        assert np.all(np.abs(g[1:7] - r[1:7]) <= 2 * np.spacing(np.abs(r[1:7]))), (g[1:7], r[1:7])
+        moments_close(g, r, rtol=1e-15)
+        moments_close(B.moments(beam, ws).cpu().numpy(), r, rtol=1e-13)
+
+
 @pytest.mark.parametrize("frac", [0.0, 0.003, 0.05, 0.5, 1.0])
 def test_compaction_order(torch, frac):
     rng = np.random.default_rng(int(frac * 1000) + 1)
