@@ -28,6 +28,10 @@
 #include "reduce.h"
 #include "surrdev.h"
 
+#ifndef INFER_NT
+#define INFER_NT 2
+#endif
+
 namespace trk {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -230,27 +234,26 @@ __device__ __forceinline__ f32x16 mma32(f32x16 c, bf16x8 a, bf16x8 b) {
 // ahead and the activation fragments (from LDS) one step ahead, so a step's
 // matrix products wait only for data requested two to three steps earlier.
 // The first step starts from a zero accumulator operand.
-template <int kX2, int KS>
-__device__ __forceinline__ void kloop32(f32x16 (&acc)[2][2], const uint16_t *__restrict__ w,
+template <int kX2, int KS, int NT>
+__device__ __forceinline__ void kloop32(f32x16 (&acc)[2][NT], const uint16_t *__restrict__ w,
                                         int wstride, int f0, const uint16_t *bh,
                                         const uint16_t *bl, int bstride) {
   constexpr int kA = KS < 3 ? KS : 3;  // weight steps in flight
   const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
   const uint16_t *wr0 = w + static_cast<size_t>(f0 + r) * wstride + 8 * h;
   const uint16_t *wr1 = wr0 + static_cast<size_t>(32) * wstride;
-  const uint16_t *b0 = bh + r * bstride + 8 * h, *b1 = b0 + 32 * bstride;
-  const uint16_t *c0 = bl + r * bstride + 8 * h, *c1 = c0 + 32 * bstride;
-  bf16x8 a[kA][2], x[2][2], y[2][2];
+  const uint16_t *b0 = bh + r * bstride + 8 * h;
+  const uint16_t *c0 = bl + r * bstride + 8 * h;
+  bf16x8 a[kA][2], x[2][NT], y[2][NT];
 #pragma unroll
   for (int q = 0; q < kA; ++q) {
     a[q][0] = ld8(wr0 + 16 * q);
     a[q][1] = ld8(wr1 + 16 * q);
   }
-  x[0][0] = ld8(b0);
-  x[0][1] = ld8(b1);
-  if constexpr (kX2) {
-    y[0][0] = ld8(c0);
-    y[0][1] = ld8(c1);
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    x[0][nt] = ld8(b0 + 32 * nt * bstride);
+    if constexpr (kX2) y[0][nt] = ld8(c0 + 32 * nt * bstride);
   }
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
@@ -260,11 +263,10 @@ __device__ __forceinline__ void kloop32(f32x16 (&acc)[2][2], const uint16_t *__r
     // the L2 latency every step)
     __builtin_amdgcn_sched_barrier(0);
     if (s + 1 < KS) {
-      x[nxt][0] = ld8(b0 + 16 * (s + 1));
-      x[nxt][1] = ld8(b1 + 16 * (s + 1));
-      if constexpr (kX2) {
-        y[nxt][0] = ld8(c0 + 16 * (s + 1));
-        y[nxt][1] = ld8(c1 + 16 * (s + 1));
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        x[nxt][nt] = ld8(b0 + 32 * nt * bstride + 16 * (s + 1));
+        if constexpr (kX2) y[nxt][nt] = ld8(c0 + 32 * nt * bstride + 16 * (s + 1));
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -272,13 +274,13 @@ __device__ __forceinline__ void kloop32(f32x16 (&acc)[2][2], const uint16_t *__r
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
         acc[mt][nt] = mma32(s == 0 ? z : acc[mt][nt], a[sa][mt], x[cur][nt]);
     if constexpr (kX2) {
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mma32(acc[mt][nt], a[sa][mt], y[cur][nt]);
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mma32(acc[mt][nt], a[sa][mt], y[cur][nt]);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (s + kA < KS) {
@@ -291,8 +293,8 @@ __device__ __forceinline__ void kloop32(f32x16 (&acc)[2][2], const uint16_t *__r
 
 // bias, SiLU, skip (kFirst: none), the new activations as hi (and lo) bf16
 // into the tile at their positions; prev keeps them in FP32
-template <int kX2, bool kFirst>
-__device__ __forceinline__ void epi32(const f32x16 (&acc)[2][2], f32x16 (&prev)[2][2],
+template <int kX2, bool kFirst, int NT>
+__device__ __forceinline__ void epi32(const f32x16 (&acc)[2][NT], f32x16 (&prev)[2][NT],
                                       const float *__restrict__ bias, uint16_t *hh, uint16_t *hl,
                                       int f0) {
   const int l = threadIdx.x & 63, r = l & 31, h = l >> 5;
@@ -308,7 +310,7 @@ __device__ __forceinline__ void epi32(const f32x16 (&acc)[2][2], f32x16 (&prev)[
       bb[4 * i + 3] = q.w;
     }
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       float v[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -333,16 +335,23 @@ __device__ __forceinline__ void epi32(const f32x16 (&acc)[2][2], f32x16 (&prev)[
   }
 }
 
+// Particles per inference workgroup: 32 * kInferNT (each wave holds
+// kInferNT 32-particle column tiles of its 64 features)
+constexpr int kInferNT = INFER_NT;
+constexpr int kIRows = 32 * kInferNT;
+constexpr int kOutParts = 4 / kInferNT;  // output layer: K split over the waves
+constexpr int kInferWaves = kInferNT == 4 ? 1 : (kInferNT == 2 ? 2 : 3);  // waves per SIMD the LDS allows
+
 // LDS of one inference workgroup
 struct InferLds {
-  uint16_t hh[kRows * kLds];
-  uint16_t hl[kRows * kLds];
-  uint16_t uh[kRows * kULds2];
-  uint16_t ul[kRows * kULds2];
-  float op[2][kRows * 8];  // output-layer K halves
+  uint16_t hh[kIRows * kLds];
+  uint16_t hl[kIRows * kLds];
+  uint16_t uh[kIRows * kULds2];
+  uint16_t ul[kIRows * kULds2];
+  float op[kOutParts][kIRows * 8];  // output-layer K parts
 };
 
-// thread t < 64: particle t's normalised inputs (s ignored) as hi/lo bf16
+// thread t < kIRows: particle t's normalised inputs (s ignored) as hi/lo bf16
 __device__ __forceinline__ void put_row(InferLds &L, int t, const float (&u)[kMlpIn]) {
   uint32_t ph[8] = {}, pl[8] = {};
 #pragma unroll
@@ -359,39 +368,41 @@ __device__ __forceinline__ void put_row(InferLds &L, int t, const float (&u)[kMl
   *reinterpret_cast<uint4 *>(ul + 8) = uint4{pl[4], pl[5], pl[6], pl[7]};
 }
 
-// The network for the 64 particles whose inputs are in L.uh/L.ul; thread
-// t < 64 reads output k of particle t as out(L, t, k) afterwards.
+// The network for the kIRows particles whose inputs are in L.uh/L.ul;
+// thread t < kIRows reads output k of particle t as out_of(m, L, t, k).
 template <int kX2>
 __device__ void infer_tile32(const MlpDev &m, InferLds &L) {
+  constexpr int NT = kInferNT;
   const int l = threadIdx.x & 63, r = l & 31, h = l >> 5, w = threadIdx.x >> 6, f0 = 64 * w;
   const uint16_t *wi = m.wi;
-  f32x16 acc[2][2], prev[2][2];
-  kloop32<kX2, kMlpInK / 16>(acc, wi, kMlpInK, f0, L.uh, L.ul, kULds2);
-  epi32<kX2, true>(acc, prev, m.b1, L.hh, L.hl, f0);
+  f32x16 acc[2][NT], prev[2][NT];
+  kloop32<kX2, kMlpInK / 16, NT>(acc, wi, kMlpInK, f0, L.uh, L.ul, kULds2);
+  epi32<kX2, true, NT>(acc, prev, m.b1, L.hh, L.hl, f0);
   __syncthreads();
-  kloop32<kX2, kMlpHid / 16>(acc, wi + kOffW2i, kMlpHid, f0, L.hh, L.hl, kLds);
+  kloop32<kX2, kMlpHid / 16, NT>(acc, wi + kOffW2i, kMlpHid, f0, L.hh, L.hl, kLds);
   __syncthreads();  // every wave has read h1 before it is overwritten
-  epi32<kX2, false>(acc, prev, m.b2, L.hh, L.hl, f0);
+  epi32<kX2, false, NT>(acc, prev, m.b2, L.hh, L.hl, f0);
   __syncthreads();
-  kloop32<kX2, kMlpHid / 16>(acc, wi + kOffW3i, kMlpHid, f0, L.hh, L.hl, kLds);
+  kloop32<kX2, kMlpHid / 16, NT>(acc, wi + kOffW3i, kMlpHid, f0, L.hh, L.hl, kLds);
   __syncthreads();
-  epi32<kX2, false>(acc, prev, m.b3, L.hh, L.hl, f0);
+  epi32<kX2, false, NT>(acc, prev, m.b3, L.hh, L.hl, f0);
   __syncthreads();
-  // output layer: wave w takes particles 32(w&1).. and K steps 8(w>>1)..+7
+  // output layer: wave w takes particles 32(w % NT).. and K part w / NT
   {
-    const int nt = w & 1, kh = w >> 1;
-    const uint16_t *wa = wi + kOffW4i + r * kMlpHid + 8 * h + 128 * kh;
-    const uint16_t *xb = L.hh + (32 * nt + r) * kLds + 8 * h + 128 * kh;
-    const uint16_t *xl = L.hl + (32 * nt + r) * kLds + 8 * h + 128 * kh;
+    constexpr int kKS = (kMlpHid / 16) / kOutParts;  // K steps per part
+    const int nt = w % NT, kp = w / NT;
+    const uint16_t *wa = wi + kOffW4i + r * kMlpHid + 8 * h + 16 * kKS * kp;
+    const uint16_t *xb = L.hh + (32 * nt + r) * kLds + 8 * h + 16 * kKS * kp;
+    const uint16_t *xl = L.hl + (32 * nt + r) * kLds + 8 * h + 16 * kKS * kp;
     f32x16 o = {};
 #pragma unroll 2
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < kKS; ++s) {
       const bf16x8 a = ld8(wa + 16 * s);
       o = mma32(o, a, ld8(xb + 16 * s));
       if constexpr (kX2) o = mma32(o, a, ld8(xl + 16 * s));
     }
     // element j (i = 0) holds output 4h + j of particle 32nt + r
-    float *op = L.op[kh] + (32 * nt + r) * 8 + 4 * h;
+    float *op = L.op[kp] + (32 * nt + r) * 8 + 4 * h;
     if (h == 0) {
       op[0] = o[0];
       op[1] = o[1];
@@ -406,7 +417,10 @@ __device__ void infer_tile32(const MlpDev &m, InferLds &L) {
 }
 
 __device__ __forceinline__ float out_of(const MlpDev &m, const InferLds &L, int t, int k) {
-  return (L.op[0][t * 8 + k] + L.op[1][t * 8 + k]) + m.b4[k];
+  float v = L.op[0][t * 8 + k];
+#pragma unroll
+  for (int q = 1; q < kOutParts; ++q) v += L.op[q][t * 8 + k];
+  return v + m.b4[k];
 }
 
 // input tile: 64 rows x 32 (6 used, s column zero) as hi/lo bf16
@@ -451,12 +465,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_infer_copy(const MlpDev m) {
 // ------------------------------------------------------------------ forward
 // o = MLP(u) for rows of u[n][8] (columns 0..5; column 4 ignored) -> out[n][8]
 template <int kX2>
-__global__ __launch_bounds__(kBlock, 2) void k_mlp_forward(const MlpDev m, const float *__restrict__ u,
+__global__ __launch_bounds__(kBlock, kInferWaves) void k_mlp_forward(const MlpDev m, const float *__restrict__ u,
                                                            int64_t n, float *__restrict__ out) {
   __shared__ __attribute__((aligned(16))) InferLds L;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kIRows;
   const int t = threadIdx.x;
-  if (t < kRows) {
+  if (t < kIRows) {
     float uu[kMlpIn] = {};
     if (row0 + t < n)
 #pragma unroll
@@ -465,7 +479,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_mlp_forward(const MlpDev m, const
   }
   __syncthreads();
   infer_tile32<kX2>(m, L);
-  if (t < kRows && row0 + t < n) {
+  if (t < kIRows && row0 + t < n) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) out[(row0 + t) * 8 + k] = k < kMlpOut ? out_of(m, L, t, k) : 0.0f;
   }
@@ -476,18 +490,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_mlp_forward(const MlpDev m, const
 // place (x, x', y, y', s; delta unchanged).  Thread t < 64 of a workgroup
 // holds particle t of the tile in FP64 from its load to its store.
 template <int kX2>
-__global__ __launch_bounds__(kBlock, 2) void k_surr_infer(const MlpDev m, const SurrDev c,
+__global__ __launch_bounds__(kBlock, kInferWaves) void k_surr_infer(const MlpDev m, const SurrDev c,
                                                           const BeamPtrs6 b,
                                                           const uint32_t *__restrict__ adm,
                                                           const int64_t *__restrict__ n_adm) {
   __shared__ __attribute__((aligned(16))) InferLds L;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kIRows;
   const int64_t na = *n_adm;
   if (row0 >= na) return;  // whole workgroup
   const int t = threadIdx.x;
   double z[6];
   int64_t idx = -1;
-  if (t < kRows) {
+  if (t < kIRows) {
     float uu[kMlpIn] = {};
     if (row0 + t < na) {
       idx = adm[row0 + t];
@@ -720,7 +734,7 @@ hipError_t launch_infer_copy(const MlpDev &m, hipStream_t st) {
 
 hipError_t launch_mlp_forward(const MlpDev &m, const float *u, int64_t n, float *out, int x2,
                               hipStream_t st) {
-  const int64_t grid = (n + kRows - 1) / kRows;
+  const int64_t grid = (n + kIRows - 1) / kIRows;
   if (grid == 0) return hipSuccess;
   if (hipError_t e = launch_infer_copy(m, st); e != hipSuccess) return e;
   if (x2)
@@ -733,7 +747,7 @@ hipError_t launch_mlp_forward(const MlpDev &m, const float *u, int64_t n, float 
 hipError_t launch_surr_infer(const MlpDev &m, const SurrDev &c, const BeamPtrs6 &b,
                              const uint32_t *adm, const int64_t *n_adm, int64_t n_total, int x2,
                              hipStream_t st) {
-  const int64_t grid = (n_total + kRows - 1) / kRows;
+  const int64_t grid = (n_total + kIRows - 1) / kIRows;
   if (grid == 0) return hipSuccess;
   if (hipError_t e = launch_infer_copy(m, st); e != hipSuccess) return e;
   if (x2)
