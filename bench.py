@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--sigma-scale", type=float, default=1.0,
                     help="scale the Gaussian beam's sigmas (0.1: nobody is lost)")
     ap.add_argument("--mib", type=int, default=1024, help="copycal: MiB copied")
+    ap.add_argument("--ppt", type=int, default=0,
+                    help="particles per thread of the fused runs (0: automatic)")
     return ap.parse_args()
 
 
@@ -308,7 +310,7 @@ def track_workload(wl, args, n=None, steps=None, warm=None, fusion=None, passes=
     def one_step(i):
         B.track(beams[i], L, pps, ws, seed=7, first_pass=0, p_ref=p_ref,
                 moments=mom if use_mom else None, wake_mode=wake_mode,
-                max_elems_per_launch=fusion, stream=stream)
+                max_elems_per_launch=fusion, run_ppt=args.ppt, stream=stream)
 
     def timed(i0, i1):
         t0 = torch.cuda.Event(enable_timing=True)
