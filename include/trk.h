@@ -170,7 +170,10 @@ size_t trk_workspace_size(const trk_lattice *lat, int64_t n_total);
  * depend on the fusion depth.  Returns after enqueuing; the beam is
  * reordered (alive set first) when the last kernel completes.  With no
  * passes, no elements or n_total = 0 nothing is enqueued and opts.moments
- * is left as it was. */
+ * is left as it was.  The call enqueues kernels only (no copies, fills or
+ * allocations, and its launch sequence depends on the lattice and options,
+ * not on device data), so it may be captured into a HIP graph; a replay
+ * repeats the captured call on the same buffers. */
 int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes, const trk_opts *opts,
               void *workspace, size_t workspace_bytes, void *stream);
 
