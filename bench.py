@@ -48,7 +48,7 @@ WAKES = ("WAKE", "TRWAKE")
 # scaled by 2.000, WRITE_SIZE by 1.000, the factors a 1 GiB copy gives),
 # averaged over the runs of one pass (profiles/*_hbm_bytes.md); absent until
 # measured for the current kernel.
-TRAFFIC_PER_LAUNCH = {("bc", 0): 101947278, ("roof", 1): 734090445}
+TRAFFIC_PER_LAUNCH = {("bc", 0): 101936697, ("roof", 1): 734090445}
 # FP64 vector peak (dense, FMA = 2 flops) and the FP64 flops of one
 # particle-element step of each lattice: SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + MUL
 # + ADD + TRANS per wave instruction) x 64 lanes over the exact steps of a
