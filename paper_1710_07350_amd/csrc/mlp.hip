@@ -4,13 +4,15 @@
 //
 // Network (6 -> 256 -> 256 -> 256 -> 6): h1 = silu(W1 u + b1),
 // h2 = h1 + silu(W2 h1 + b2), h3 = h2 + silu(W3 h2 + b3), o = W4 h3 + b4.
-// Matrix products run on v_mfma_f32_16x16x32_bf16 (bfloat16 operands, FP32
-// accumulation).  Weights enter as bfloat16 rounded from the FP32 master copy.
+// Training runs its matrix products on v_mfma_f32_16x16x32_bf16 and inference
+// on v_mfma_f32_32x32x16_bf16 (its tile is described further down); both take
+// bfloat16 operands with FP32 accumulation.  Weights enter as bfloat16
+// rounded from the FP32 master copy.
 // Activations enter either as one bfloat16 (TRK_MLP_BF16) or as the sum of
 // two (TRK_MLP_BF16X2: hi = bf16(h), lo = bf16(h - hi), two products into
 // one accumulator), which carries 16 significant bits.
 //
-// Work split: a workgroup of four waves owns a tile of 64 rows (particles).
+// Work split (training): a workgroup of four waves owns a tile of 64 rows (particles).
 // The tile's activations live in LDS, row-major, as the A operand; wave w
 // computes output columns [64w, 64w + 64) of every hidden layer for all 64
 // rows (4 x 4 MFMA tiles), reading its weight rows straight from L2 as the B
