@@ -533,3 +533,27 @@ def test_ring_full_size_sampled(torch):
     assert np.array_equal(g["lost_at"][rows], r["lost_at"])
     assert np.array_equal(g["z"][:, rows], r["z"])
     assert (g["lost_at"][: g["n_alive"]] < 0).all()
+
+
+@pytest.mark.parametrize("shape", ["one", "same_s", "two_s"])
+def test_bunch_compressor_degenerate_beams(torch, shape):
+    """Wakes on degenerate bunches: a single particle, a bunch whose
+    particles all share one s (histogram range of width zero: every count in
+    bin 0, every lag zero) and a bunch on two values of s.  Binary64 wakes
+    bit-exact with the oracle; FP32 matrix-core wakes within their bound."""
+    n = 1 if shape == "one" else 5000
+    d = inputs.gaussian_beam(n, seed=12, chirp=inputs.BC_CHIRP)
+    if shape == "same_s":
+        d["z"][4][:] = 2.5e-4
+    elif shape == "two_s":
+        d["z"][4][:] = np.where(np.arange(n) % 3 == 0, -1e-3, 7e-4)
+    lat = inputs.bc_lattice()
+    g = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64)
+    r = run_oracle(lat, d, 1, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+    f = run_gpu(lat, d, 1, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA)
+    assert f["n_alive"] == r["n_alive"] == n
+    for k in (0, 1, 2, 3):
+        assert np.array_equal(f["z"][k], r["z"][k])
+    bd = bc_bound_on_delta(d, lat, n)
+    assert np.abs(f["z"][5] - r["z"][5]).max() <= bd
