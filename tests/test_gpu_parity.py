@@ -557,3 +557,18 @@ def test_bunch_compressor_degenerate_beams(torch, shape):
         assert np.array_equal(f["z"][k], r["z"][k])
     bd = bc_bound_on_delta(d, lat, n)
     assert np.abs(f["z"][5] - r["z"][5]).max() <= bd
+
+
+def test_bunch_compressor_streaming_runs(torch):
+    """Non-temporal loads and stores in the two-coordinate kick runs (the
+    form the runs take when s and delta exceed the Infinity Cache, as at 4e7
+    particles), forced here on 100001 particles: binary64 wakes bit-exact with
+    the oracle over two passes, FP32 wakes bit-identical to the cached form."""
+    lat = inputs.bc_lattice()
+    d = inputs.gaussian_beam(100_001, seed=14, chirp=inputs.BC_CHIRP)
+    g = run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP64, run_nt=1)
+    r = run_oracle(lat, d, 2, p_ref=inputs.BC_P0_EV)
+    assert_bit_exact(g, r)
+    f = [run_gpu(lat, d, 2, p_ref=inputs.BC_P0_EV, wake_mode=B.WAKE_FP32_MFMA, run_nt=nt)
+         for nt in (1, -1)]
+    assert np.array_equal(f[0]["z"], f[1]["z"]) and np.array_equal(f[0]["id"], f[1]["id"])
