@@ -687,6 +687,12 @@ struct Launch {
 extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
                          const trk_opts *opts, void *workspace, size_t workspace_bytes_,
                          void *stream) {
+  return trk::host::track_impl(beam, lat, passes, opts, workspace, workspace_bytes_, stream, true);
+}
+
+int trk::host::track_impl(trk_beam *beam, const trk_lattice *lat, int32_t passes,
+                          const trk_opts *opts, void *workspace, size_t workspace_bytes_,
+                          void *stream, bool compact_end) {
   if (lat == nullptr || opts == nullptr) return fail(TRK_EINVAL, "lattice or opts is NULL");
   if (passes < 0) return fail(TRK_EINVAL, "passes < 0");
   if (opts->wake_mode != TRK_WAKE_FP64 && opts->wake_mode != TRK_WAKE_FP32_MFMA)
@@ -958,7 +964,7 @@ extern "C" int trk_track(trk_beam *beam, const trk_lattice *lat, int32_t passes,
       dirty = false;
     }
   }
-  if (dirty)
+  if (dirty && compact_end)
     HIP_TRY(launch_compact(z, beam->id, beam->lost_at, beam->n_alive, beam->n_total, w, st),
             "compact");
   return TRK_OK;

@@ -22,6 +22,12 @@ void beam_ptrs(const trk_beam *b, double *z[6]);
 // classes: 0 fused element run, 1 surrogate network inference, 2 wake
 // histogram, 3 wake convolution
 hipError_t profiled_call(int cls, hipStream_t st, const std::function<hipError_t()> &launch);
+
+// trk_track; with compact_end false a beam that lost particles is left
+// uncompacted at the end of the call (lost particles keep their slots, marked
+// in lost_at), for a caller that reorders the beam itself afterwards
+int track_impl(trk_beam *beam, const trk_lattice *lat, int32_t passes, const trk_opts *opts,
+               void *workspace, size_t workspace_bytes, void *stream, bool compact_end);
 }  // namespace host
 }  // namespace trk
 

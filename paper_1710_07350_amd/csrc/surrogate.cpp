@@ -781,13 +781,16 @@ extern "C" int trk_surrogate_apply(const trk_surrogate *s, const trk_mlp *m, trk
   HIP_TRY(launch_gate_split(bp, beam->n_alive, beam->n_total, s->c, w.flags, w.blk, w.adm, w.rej,
                             w.counts, st),
           "gate");
-  // fallback: the rejected particles through the section element by element
+  // fallback: the rejected particles through the section element by element,
+  // left in gather order (their losses marked, not compacted), so the
+  // scatter back writes the beam in index order; the whole beam is compacted
+  // once at the end
   HIP_TRY(launch_gather(bp, w.rej, w.counts + 1, beam->n_total, stage, w.stage_n, nullptr, 1, st),
           "gather");
   trk_opts op{};
   op.p_ref_eV = 1e9;
   op.first_pass = first_pass;
-  if (int r = trk_track(&sb, s->sec, 1, &op, w.track_ws, w.track_bytes, st)) return r;
+  if (int r = track_impl(&sb, s->sec, 1, &op, w.track_ws, w.track_bytes, st, false)) return r;
   const MlpDev md = dev_of(m);
   HIP_TRY(profiled_call(1, st,
                         [&] {
